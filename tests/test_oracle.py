@@ -1,0 +1,313 @@
+"""Pins for the CPU oracle: facts fixed by the paper and by mathematics.
+
+Each pin is chosen so that a plausible slip in the oracle (a sign in the
+Hamilton table, a swapped operand, a transposed block, a dropped term) fails
+at least one of them; test_planted_mistakes checks that claim on mutated
+copies of the product written in numpy.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02081_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+UNIT_COMP = {"1": 0, "i": 1, "j": 2, "k": 3}
+
+
+def _unit(u, n=3, imag=False):
+    """Identity-block matrix of unit u (times the commuting i if imag)."""
+    M = np.zeros((8, n, n))
+    M[UNIT_COMP[u] + (4 if imag else 0)] = np.eye(n)
+    return M
+
+
+def _scalar(vals):
+    return np.asarray(vals, dtype=np.float64).reshape(8, 1, 1)
+
+
+# --------------------------------------------------------------------------
+# Worked values (tests/golden)
+# --------------------------------------------------------------------------
+def test_unit_table_bit_exact():
+    """Unit relations of Sec. II A on identity blocks, bit-exact."""
+    with open(os.path.join(GOLDEN, "quaternion_units.json")) as f:
+        g = json.load(f)
+    for a, b in itertools.product(g["units"], repeat=2):
+        sign, unit = g["table"][g["units"].index(a)][g["units"].index(b)]
+        C = oracle.gemm(_unit(a), _unit(b))
+        expect = sign * _unit(unit)
+        assert np.array_equal(C, expect), (a, b)
+
+
+def test_i_j_k_product_is_minus_one():
+    C = oracle.gemm(oracle.gemm(_unit("i"), _unit("j")), _unit("k"))
+    assert np.array_equal(C, -_unit("1"))
+    for u in "ijk":
+        assert np.array_equal(oracle.gemm(_unit(u), _unit(u)), -_unit("1"))
+
+
+def test_commuting_imaginary_unit():
+    """The field unit i (component 5) squares to -1 and commutes with i,j,k."""
+    ii = oracle.gemm(_unit("1", imag=True), _unit("1", imag=True))
+    assert np.array_equal(ii, -_unit("1"))
+    for u in "ijk":
+        left = oracle.gemm(_unit("1", imag=True), _unit(u))
+        right = oracle.gemm(_unit(u), _unit("1", imag=True))
+        assert np.array_equal(left, right)
+        assert np.array_equal(left, _unit(u, imag=True))
+
+
+def test_worked_scalar_products():
+    with open(os.path.join(GOLDEN, "scalar_products.json")) as f:
+        g = json.load(f)
+    for case in g["cases"]:
+        C = oracle.gemm(_scalar(case["a"]), _scalar(case["b"]))
+        assert np.array_equal(C.reshape(8), np.asarray(case["c"], dtype=np.float64)), case["name"]
+
+
+# --------------------------------------------------------------------------
+# Algebraic structure
+# --------------------------------------------------------------------------
+def test_associativity():
+    rng = np.random.default_rng(11)
+    A = inputs.blocks(rng, 9, 13)
+    B = inputs.blocks(rng, 13, 7)
+    C = inputs.blocks(rng, 7, 11)
+    left = oracle.gemm(oracle.gemm(A, B), C)
+    right = oracle.gemm(A, oracle.gemm(B, C))
+    assert oracle.rel_frobenius(left, right) < 1e-14
+
+
+def test_noncommutative():
+    rng = np.random.default_rng(12)
+    A = inputs.blocks(rng, 6, 6)
+    B = inputs.blocks(rng, 6, 6)
+    assert oracle.rel_frobenius(oracle.gemm(A, B), oracle.gemm(B, A)) > 0.1
+
+
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (5, 3, 4), (16, 33, 8), (64, 64, 64)])
+def test_isomorph_homomorphism(m, k, n):
+    """Z(AB) = Z(A) Z(B) with Z the 2m x 2n complex isomorph of Sec. III,
+    checked against numpy's complex GEMM (a textbook routine)."""
+    A, B = inputs.pair(m, k, n, "normal", seed=m * 100 + n)
+    C = oracle.gemm(A, B)
+    ZC = oracle.iso(A) @ oracle.iso(B)
+    assert np.linalg.norm(oracle.iso(C) - ZC) <= 1e-14 * np.linalg.norm(ZC)
+    assert oracle.rel_frobenius(oracle.iso_inv(ZC), C) < 1e-14
+
+
+def test_isomorph_round_trip_and_norm():
+    rng = np.random.default_rng(3)
+    M = inputs.blocks(rng, 5, 7)
+    assert np.array_equal(oracle.iso_inv(oracle.iso(M)), M)
+    # ||Z(M)||_F^2 = 2 sum_c ||M_c||_F^2
+    assert np.isclose(np.linalg.norm(oracle.iso(M)) ** 2, 2 * np.sum(M ** 2), rtol=1e-14)
+
+
+def _pauli_2x2(q):
+    """2x2 complex matrix of a scalar biquaternion by eqs. TRG-in-C / qmap1:
+    q = s + v_z i + v_y j + v_x k  ->  s I + v_z (i sz) + v_y (i sy) + v_x (i sx)."""
+    s = q[0] + 1j * q[4]
+    vz = q[1] + 1j * q[5]
+    vy = q[2] + 1j * q[6]
+    vx = q[3] + 1j * q[7]
+    return [[s + 1j * vz, vy + 1j * vx],
+            [-vy + 1j * vx, s - 1j * vz]]
+
+
+def _from_pauli(P):
+    """Coefficients back from a 2x2 matrix: with basis B_u = i sigma_u,
+    coef_u = -tr(P B_u) / 2 and s = tr(P) / 2."""
+    s = (P[0][0] + P[1][1]) / 2
+    vz = -(1j * P[0][0] - 1j * P[1][1]) / 2           # B_z = [[i,0],[0,-i]]
+    vy = -(-P[0][1] + P[1][0]) / 2                     # B_y = [[0,1],[-1,0]]
+    vx = -(1j * P[0][1] + 1j * P[1][0]) / 2           # B_x = [[0,i],[i,0]]
+    return [s.real, vz.real, vy.real, vx.real, s.imag, vz.imag, vy.imag, vx.imag]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_bruteforce_pauli(n):
+    """Pure-Python loops over 2x2 complex Pauli blocks (Sec. II A)."""
+    A, B = inputs.pair(n, n, n, "uniform", seed=40 + n)
+    C = oracle.gemm(A, B)
+    for i in range(n):
+        for j in range(n):
+            acc = [[0j, 0j], [0j, 0j]]
+            for k in range(n):
+                P = _pauli_2x2(A[:, i, k])
+                Q = _pauli_2x2(B[:, k, j])
+                for r in range(2):
+                    for c in range(2):
+                        acc[r][c] += P[r][0] * Q[0][c] + P[r][1] * Q[1][c]
+            ref = _from_pauli(acc)
+            assert np.allclose(C[:, i, j], ref, rtol=0, atol=1e-14), (i, j)
+
+
+def test_det_multiplicative_n1():
+    A, B = inputs.pair(1, 1, 1, "normal", seed=9)
+    d = lambda M: np.linalg.det(oracle.iso(M))
+    assert np.isclose(d(oracle.gemm(A, B)), d(A) * d(B), rtol=1e-13)
+
+
+def test_integer_inputs_exact():
+    """Integer inputs: every intermediate is exact, so the oracle must equal
+    the exact isomorph product (int64 arithmetic) bit for bit."""
+    A, B = inputs.pair(24, 40, 16, "int", seed=5, bound=1024)
+    C = oracle.gemm(A, B)
+    ZA, ZB = oracle.iso(A), oracle.iso(B)
+    XA, YA = ZA.real.astype(np.int64), ZA.imag.astype(np.int64)
+    XB, YB = ZB.real.astype(np.int64), ZB.imag.astype(np.int64)
+    Zre = XA @ XB - YA @ YB
+    Zim = XA @ YB + YA @ XB
+    exact = oracle.iso_inv(Zre.astype(np.float64) + 1j * Zim.astype(np.float64))
+    assert np.array_equal(C, exact)
+
+
+def test_transpose_conj_herm_rules():
+    """Sign rules of Sec. III equal Z^T, conj(Z), Z^H, and give the
+    (anti-)homomorphisms (AB)^T = B^T A^T, (AB)* = A* B*, (AB)^+ = B^+ A^+."""
+    A, B = inputs.pair(6, 5, 4, "normal", seed=21)
+    Z = oracle.iso(A)
+    assert np.array_equal(oracle.iso(oracle.transpose(A)), Z.T)
+    assert np.array_equal(oracle.iso(oracle.conj(A)), Z.conj())
+    assert np.array_equal(oracle.iso(oracle.herm(A)), Z.conj().T)
+    AB = oracle.gemm(A, B)
+    tol = 1e-14
+    assert oracle.rel_frobenius(oracle.transpose(AB),
+                                oracle.gemm(oracle.transpose(B), oracle.transpose(A))) < tol
+    assert oracle.rel_frobenius(oracle.conj(AB), oracle.gemm(oracle.conj(A), oracle.conj(B))) < tol
+    assert oracle.rel_frobenius(oracle.herm(AB), oracle.gemm(oracle.herm(B), oracle.herm(A))) < tol
+
+
+def test_trace_rule():
+    rng = np.random.default_rng(8)
+    M = inputs.blocks(rng, 7, 7)
+    assert np.isclose(oracle.trace(M), np.trace(oracle.iso(M)), rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Subalgebras reduce to textbook products (Sec. III A, last paragraph)
+# --------------------------------------------------------------------------
+def test_real_subalgebra_is_dgemm():
+    A, B = inputs.pair(20, 30, 10, "normal", seed=31, mask_a=inputs.REAL, mask_b=inputs.REAL)
+    C = oracle.gemm(A, B)
+    assert np.allclose(C[0], A[0] @ B[0], rtol=0, atol=1e-13)
+    assert not np.any(C[1:])
+
+
+def test_complex_subalgebra_is_zgemm():
+    A, B = inputs.pair(20, 30, 10, "normal", seed=32, mask_a=inputs.COMPLEX, mask_b=inputs.COMPLEX)
+    C = oracle.gemm(A, B)
+    ref = (A[0] + 1j * A[4]) @ (B[0] + 1j * B[4])
+    assert np.allclose(C[0] + 1j * C[4], ref, rtol=0, atol=1e-13)
+    assert not np.any(C[[1, 2, 3, 5, 6, 7]])
+
+
+def test_real_quaternion_closure():
+    A, B = inputs.pair(12, 12, 12, "normal", seed=33, mask_a=inputs.REAL_QUAT,
+                       mask_b=inputs.REAL_QUAT)
+    C = oracle.gemm(A, B)
+    assert not np.any(C[4:])
+
+
+# --------------------------------------------------------------------------
+# Degenerate shapes and special values
+# --------------------------------------------------------------------------
+def test_degenerate_shapes():
+    A, B = inputs.pair(4, 0, 5, "uniform", seed=1)
+    assert np.array_equal(oracle.gemm(A, B), np.zeros((8, 4, 5)))
+    A, B = inputs.pair(0, 3, 5, "uniform", seed=1)
+    assert oracle.gemm(A, B).shape == (8, 0, 5)
+
+
+def test_nan_spreads_to_row():
+    A, B = inputs.pair(6, 6, 6, "uniform", seed=2)
+    A[3, 2, 4] = np.nan
+    C = oracle.gemm(A, B)
+    assert np.all(np.isnan(C[:, 2, :]))
+    others = np.delete(C, 2, axis=1)
+    assert not np.any(np.isnan(others))
+
+
+# --------------------------------------------------------------------------
+# Hermitian-structured generator (used at n = 16384 / 24576)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["fock", "density"])
+def test_hermitian_generator(kind):
+    n = 24
+    p = inputs.hermitian_params(n, seed=3, kind=kind)
+    M = inputs.hermitian_blocks(p).numpy()
+    Z = oracle.iso(M)
+    assert np.allclose(Z, Z.conj().T, rtol=0, atol=1e-15)
+    ev = np.sort(np.linalg.eigvalsh(Z))
+    assert np.allclose(ev, np.sort(p["lam"]), rtol=0, atol=1e-12)
+    # Hermitian biquaternion: M^+ = M, i.e. pattern [S, A, A, A, A, S, S, S]
+    sym = [1, -1, -1, -1, -1, 1, 1, 1]
+    for c in range(8):
+        assert np.allclose(M[c], sym[c] * M[c].T, rtol=0, atol=1e-15), c
+    assert np.allclose(oracle.herm(M), M, rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# The pins above catch plausible slips: mutate a numpy restatement of the
+# oracle's definition and check that every mutant fails at least one pin,
+# while the faithful restatement passes them and equals the C oracle.
+# --------------------------------------------------------------------------
+def _np_product(A, B, mutant=None):
+    """Eq. MatrixQMultiplication with matrix coefficients (numpy)."""
+    perm = [0, 1, 2, 3, 4, 5, 6, 7]
+    if mutant == "layout_swap_ij":
+        perm = [0, 2, 1, 3, 4, 6, 5, 7]
+    A = A[perm]
+    B = B[perm]
+    S1, S2 = A[0] + 1j * A[4], B[0] + 1j * B[4]
+    V1 = [A[3] + 1j * A[7], A[2] + 1j * A[6], A[1] + 1j * A[5]]   # (x, y, z)
+    V2 = [B[3] + 1j * B[7], B[2] + 1j * B[6], B[1] + 1j * B[5]]
+    dot = V1[0] @ V2[0] + V1[1] @ V2[1] + (0 if mutant == "drop_dot_term" else V1[2] @ V2[2])
+    s = S1 @ S2 - dot
+    cross = [V1[1] @ V2[2] - V1[2] @ V2[1],
+             V1[2] @ V2[0] - V1[0] @ V2[2],
+             V1[0] @ V2[1] - V1[1] @ V2[0]]
+    if mutant == "cross_operand_order":
+        cross = [V2[1] @ V1[2] - V2[2] @ V1[1],
+                 V2[2] @ V1[0] - V2[0] @ V1[2],
+                 V2[0] @ V1[1] - V2[1] @ V1[0]] if A.shape == B.shape else cross
+    sgn = 1.0 if mutant == "cross_sign" else -1.0
+    v = [S1 @ V2[d] + V1[d] @ S2 + sgn * cross[d] for d in range(3)]
+    if mutant == "conj_field_unit":
+        s = s.conj()
+    out = np.stack([s.real, v[2].real, v[1].real, v[0].real, s.imag, v[2].imag, v[1].imag, v[0].imag])
+    inv = np.argsort(perm)
+    return out[inv]
+
+
+def _pins_hold(product) -> bool:
+    with open(os.path.join(GOLDEN, "quaternion_units.json")) as f:
+        g = json.load(f)
+    for a, b in itertools.product(g["units"], repeat=2):
+        sign, unit = g["table"][g["units"].index(a)][g["units"].index(b)]
+        if not np.array_equal(product(_unit(a), _unit(b)), sign * _unit(unit)):
+            return False
+    ii = product(_unit("1", imag=True), _unit("1", imag=True))
+    if not np.array_equal(ii, -_unit("1")):
+        return False
+    A, B = inputs.pair(5, 5, 5, "normal", seed=77)
+    ZC = oracle.iso(A) @ oracle.iso(B)
+    return np.linalg.norm(oracle.iso(product(A, B)) - ZC) <= 1e-13 * np.linalg.norm(ZC)
+
+
+def test_faithful_restatement_passes_and_matches():
+    assert _pins_hold(_np_product)
+    A, B = inputs.pair(7, 6, 5, "normal", seed=78)
+    assert oracle.rel_frobenius(_np_product(A, B), oracle.gemm(A, B)) < 1e-14
+
+
+@pytest.mark.parametrize("mutant", ["cross_sign", "cross_operand_order", "drop_dot_term",
+                                    "layout_swap_ij", "conj_field_unit"])
+def test_planted_mistakes(mutant):
+    assert not _pins_hold(lambda A, B: _np_product(A, B, mutant))
