@@ -1,0 +1,144 @@
+/*
+ * bq.h -- C-ABI of the MI355X (gfx950) bilinear biquaternion GEMM library.
+ *
+ * Operation (paper Sec. II A, eq. MatrixQMultiplication; Sec. III A,
+ * eq. bilinearH with eq. cmplx-3-real-mult): C = op(A) . op(B) for
+ * matrix-valued biquaternions A in H_C^{m x k}, B in H_C^{k x n}, computed by
+ * the bilinear scheme (8 complex products formed with Gauss's three real
+ * products each: 24 real GEMMs for full biquaternions) or, when the active
+ * components make it cheaper (Sec. III A, last paragraph), by the
+ * component-wise form with absent terms omitted.
+ *
+ * Layout (Sec. III, eqs. biquat-repres and main-biquat-eqn): a biquaternion
+ * matrix is eight real FP64 blocks
+ *     comp[0..7] = [M1..M8] = [E_R, E_I, F_R, F_I, G_I, -G_R, H_I, -H_R]
+ * so the coefficient of unit 1 is comp[0] + i comp[4], of i comp[1] + i comp[5],
+ * of j comp[2] + i comp[6], of k comp[3] + i comp[7].  Every block is
+ * row-major with the same leading dimension ld (elements, ld >= cols) and
+ * lives in device memory of the handle's GPU.  All offsets are 64-bit.
+ *
+ * Ownership: the caller owns A, B, C and any workspace; they must stay valid
+ * until the work enqueued on the stream has finished.  The library keeps no
+ * pointer after a call returns.
+ *
+ * Errors: every argument check is synchronous host code and runs before
+ * anything is enqueued; on any error nothing is enqueued and C is untouched.
+ * Faults inside kernels surface at the caller's next stream synchronisation.
+ * Calls are asynchronous with respect to the host.
+ *
+ * Threading: a handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef BQ_H
+#define BQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BQ_OK = 0,
+  BQ_ERR_INVALID_VALUE = 1, /* null/negative/mismatched argument            */
+  BQ_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement  */
+  BQ_ERR_ALIAS = 3,         /* C overlaps A, B, the workspace or itself      */
+  BQ_ERR_WORKSPACE = 4,     /* workspace smaller than the minimum plan       */
+  BQ_ERR_HIP = 5,           /* a HIP runtime call failed                     */
+  BQ_ERR_ARCH = 6           /* device is not gfx950                          */
+} bq_status_t;
+
+/* op(X): N = as stored, T = biquaternion transpose, C = complex conjugate,
+ * H = Hermitian conjugate (Sec. III, sign rules for T, *, dagger).
+ * This build implements N and C; T and H return BQ_ERR_UNSUPPORTED. */
+typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
+
+/* Arithmetic of the real GEMMs.  FP64: FP64 MFMA.  The split forms slice
+ * each FP64 operand into `slices` low-precision pieces with power-of-two
+ * scaling per row (left operand) / column (right operand), multiply the
+ * pieces on MFMA with FP32 accumulation and recombine in FP64. */
+typedef enum {
+  BQ_PREC_FP64 = 0,
+  BQ_PREC_SPLIT_BF16 = 1,
+  BQ_PREC_SPLIT_FP8 = 2
+} bq_prec_t;
+
+typedef struct bq_handle_s* bq_handle_t;
+typedef void* bq_stream_t; /* a hipStream_t; NULL = the null stream */
+
+/* One matrix-valued biquaternion.  For an input, comp[c] == NULL means the
+ * component is identically zero (an "absent" component).  For an output of
+ * bq_gemm all eight pointers are required. */
+typedef struct {
+  double* comp[8];
+  int64_t rows;
+  int64_t cols;
+  int64_t ld;
+} bq_matrix_t;
+
+/* Component masks: bit c set <=> comp[c] active. */
+#define BQ_MASK_FULL 0xFFu
+#define BQ_MASK_REAL_QUATERNION 0x0Fu
+#define BQ_MASK_COMPLEX 0x11u
+#define BQ_MASK_REAL 0x01u
+
+/* Create a handle bound to HIP device `device` (BQ_ERR_ARCH if it is not
+ * gfx950, BQ_ERR_HIP if the runtime call fails).  *h receives the handle. */
+bq_status_t bq_create(bq_handle_t* h, int device);
+bq_status_t bq_destroy(bq_handle_t h);
+
+/* Static text for a status code (never NULL). */
+const char* bq_status_string(bq_status_t s);
+/* Text of the last failure detected by this host thread (never NULL). */
+const char* bq_last_error_detail(void);
+
+/* Workspace for bq_gemm.  *resident_bytes lets every pre-combined operand
+ * stay in memory at once; *min_bytes is the least the streamed plan needs
+ * (pre-combinations formed one product at a time).  Either output pointer
+ * may be NULL.  maskA/maskB as in BQ_MASK_*; op as in bq_gemm. */
+bq_status_t bq_gemm_workspace_size(int64_t m, int64_t n, int64_t k,
+                                   unsigned maskA, unsigned maskB,
+                                   bq_prec_t prec, int slices,
+                                   size_t* resident_bytes, size_t* min_bytes);
+
+/* Host-only validation of a bq_gemm call (no HIP call is made): returns what
+ * bq_gemm would return for these arguments before enqueueing anything. */
+bq_status_t bq_gemm_check(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
+                          const bq_matrix_t* B, const bq_matrix_t* C,
+                          bq_prec_t prec, int slices, const void* ws,
+                          size_t ws_bytes);
+
+/* C <- op(A) op(B), C is m x n, op(A) m x k, op(B) k x n.
+ * ws: device workspace (may be NULL when bq_gemm_workspace_size gives 0);
+ * with ws_bytes >= resident size the resident plan runs, otherwise with
+ * ws_bytes >= min size the streamed plan, otherwise BQ_ERR_WORKSPACE.
+ * m == 0 or n == 0: no-op.  k == 0: C = 0.
+ * Components of C that are structurally zero for the given input masks are
+ * written as 0.  `slices` is used by the split forms (0 = default). */
+bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB,
+                    const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C,
+                    bq_prec_t prec, int slices, void* ws, size_t ws_bytes,
+                    bq_stream_t stream);
+
+/* Subalgebra special cases (Sec. III A: real, complex and real-quaternion
+ * matrices embedded in H_C).  Same conventions as bq_gemm; only the named
+ * components of A, B and C are read or written, the rest may be NULL.
+ *   bq_re_gemm: comp[0]                     (1 real GEMM)
+ *   bq_cx_gemm: comp[0] + i comp[4]         (3 real GEMMs, Gauss)
+ *   bq_rq_gemm: comp[0..3] (real quaternion, 8 real GEMMs, bilinear) */
+bq_status_t bq_re_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B,
+                       bq_matrix_t* C, bq_stream_t stream);
+bq_status_t bq_cx_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
+                       const bq_matrix_t* B, bq_matrix_t* C, bq_stream_t stream);
+bq_status_t bq_rq_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B,
+                       bq_matrix_t* C, void* ws, size_t ws_bytes, bq_stream_t stream);
+
+/* Number of real GEMMs the planner runs for these masks (the paper's counts:
+ * 24 full, 8 real quaternion, 3 complex, 1 real).  Host only. */
+int bq_plan_real_gemms(unsigned maskA, unsigned maskB);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BQ_H */

@@ -1,8 +1,11 @@
 """Bilinear biquaternion GEMM for AMD MI355X (gfx950).
 
 The compute path is the HIP library libbq.so behind the C-ABI declared in
-include/bq.h; this package is a thin ctypes binding over it.  The binding is
-loaded on first use and raises if the library is missing: there is no CPU
-fallback.
+include/bq.h; this package is a thin ctypes binding over it.  The library is
+loaded on first use and a missing library raises: there is no CPU fallback.
 """
-__all__ = ["inputs"]
+from ._binding import (BqError, FULL, REAL_QUAT, COMPLEX, REAL, bq_gemm, re_gemm, cx_gemm,
+                       rq_gemm, workspace_size, plan_real_gemms, lib, handle, matrix, last_error)
+
+__all__ = ["BqError", "FULL", "REAL_QUAT", "COMPLEX", "REAL", "bq_gemm", "re_gemm", "cx_gemm",
+           "rq_gemm", "workspace_size", "plan_real_gemms", "lib", "handle", "matrix", "last_error"]

@@ -1,0 +1,207 @@
+"""ctypes binding of libbq.so: argument marshalling only.
+
+Every arithmetic step runs in the HIP library.  Tensors are torch float64
+device tensors shaped (8, rows, cols) (or lists of 8 tensors / None); torch
+only provides the memory, the workspace allocation and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbq.so")
+
+OPS = {"N": 0, "T": 1, "C": 2, "H": 3}
+PRECS = {"fp64": 0, "split_bf16": 1, "split_fp8": 2}
+STATUS = {0: "BQ_OK", 1: "BQ_ERR_INVALID_VALUE", 2: "BQ_ERR_UNSUPPORTED", 3: "BQ_ERR_ALIAS",
+          4: "BQ_ERR_WORKSPACE", 5: "BQ_ERR_HIP", 6: "BQ_ERR_ARCH"}
+
+FULL, REAL_QUAT, COMPLEX, REAL = 0xFF, 0x0F, 0x11, 0x01
+
+
+class BqMatrix(ctypes.Structure):
+    _fields_ = [("comp", ctypes.c_void_p * 8), ("rows", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("ld", ctypes.c_int64)]
+
+
+class BqError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        super().__init__(f"{STATUS.get(code, code)}: {detail}")
+        self.code = code
+        self.detail = detail
+
+
+_lib = None
+
+# (name, restype, argtypes) of every symbol declared in include/bq.h
+_M = ctypes.POINTER(BqMatrix)
+_SIGS = [
+    ("bq_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    ("bq_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("bq_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("bq_last_error_detail", ctypes.c_char_p, []),
+    ("bq_gemm_workspace_size", ctypes.c_int,
+     [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint, ctypes.c_uint, ctypes.c_int,
+      ctypes.c_int, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    ("bq_gemm_check", ctypes.c_int,
+     [ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]),
+    ("bq_gemm", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("bq_re_gemm", ctypes.c_int, [ctypes.c_void_p, _M, _M, _M, ctypes.c_void_p]),
+    ("bq_cx_gemm", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_void_p]),
+    ("bq_rq_gemm", ctypes.c_int,
+     [ctypes.c_void_p, _M, _M, _M, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("bq_plan_real_gemms", ctypes.c_int, [ctypes.c_uint, ctypes.c_uint]),
+]
+
+
+def lib():
+    """Load libbq.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().bq_last_error_detail().decode()
+
+
+def check(code: int) -> None:
+    if code != 0:
+        raise BqError(code, last_error())
+
+
+_handles: dict[int, ctypes.c_void_p] = {}
+
+
+def handle(device: int = 0) -> ctypes.c_void_p:
+    h = _handles.get(device)
+    if h is None:
+        h = ctypes.c_void_p()
+        check(lib().bq_create(ctypes.byref(h), device))
+        _handles[device] = h
+    return h
+
+
+def _is_tensor(x) -> bool:
+    return hasattr(x, "data_ptr") and hasattr(x, "stride")
+
+
+def matrix(X, mask: int = FULL, rows=None, cols=None) -> BqMatrix:
+    """BqMatrix over a (8, rows, cols) tensor or a list of 8 (rows, cols)
+    tensors / None.  Components outside `mask` (or None) are passed as absent."""
+    M = BqMatrix()
+    comps = list(X) if not _is_tensor(X) else [X[c] for c in range(8)]
+    if len(comps) != 8:
+        raise ValueError("a biquaternion matrix has 8 components")
+    ref = next((c for c in comps if c is not None), None)
+    if ref is None:
+        if rows is None or cols is None:
+            raise ValueError("all components absent: give rows and cols")
+        M.rows, M.cols, M.ld = rows, cols, max(1, cols)
+        return M
+    M.rows, M.cols = ref.shape
+    M.ld = ref.stride(0) if ref.shape[0] > 1 else max(1, ref.shape[1])
+    for c, t in enumerate(comps):
+        if t is None or not (mask >> c & 1):
+            M.comp[c] = None
+            continue
+        if t.shape != ref.shape or (t.shape[0] > 1 and t.stride(0) != M.ld) or t.stride(1) != 1:
+            raise ValueError("components must share shape and row-major layout")
+        M.comp[c] = t.data_ptr()
+    return M
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_size(m, n, k, mask_a=FULL, mask_b=FULL, prec="fp64", slices=0):
+    res = ctypes.c_size_t()
+    mn = ctypes.c_size_t()
+    check(lib().bq_gemm_workspace_size(m, n, k, mask_a, mask_b, PRECS[prec], slices,
+                                       ctypes.byref(res), ctypes.byref(mn)))
+    return res.value, mn.value
+
+
+def plan_real_gemms(mask_a=FULL, mask_b=FULL) -> int:
+    return lib().bq_plan_real_gemms(mask_a, mask_b)
+
+
+def bq_gemm(A, B, C=None, *, opA="N", opB="N", mask_a=FULL, mask_b=FULL, prec="fp64", slices=0,
+            workspace=None, streamed=False, stream=None):
+    """C = op(A) op(B) on the current device; returns C (8, m, n) float64."""
+    import torch
+
+    Am = matrix(A, mask_a)
+    Bm = matrix(B, mask_b)
+    m, k, n = Am.rows, Am.cols, Bm.cols
+    dev = (A if _is_tensor(A) else next(t for t in A if t is not None)).device
+    if C is None:
+        C = torch.empty((8, m, n), dtype=torch.float64, device=dev)
+    Cm = matrix(C)
+    res, mn = workspace_size(m, n, k, _mask_of(Am), _mask_of(Bm), prec, slices)
+    if workspace is None:
+        need = mn if streamed else res
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    if streamed:
+        ws_bytes = min(ws_bytes, mn)
+    check(lib().bq_gemm(handle(dev.index or 0), OPS[opA], OPS[opB], ctypes.byref(Am), ctypes.byref(Bm),
+                        ctypes.byref(Cm), PRECS[prec], slices, ctypes.c_void_p(workspace.data_ptr()),
+                        ws_bytes, _stream(stream)))
+    return C
+
+
+def _mask_of(M: BqMatrix) -> int:
+    return sum(1 << c for c in range(8) if M.comp[c])
+
+
+def re_gemm(A, B, C, stream=None):
+    """A, B, C: (rows, cols) real tensors."""
+    z = [None] * 7
+    Am, Bm, Cm = matrix([A] + z), matrix([B] + z), matrix([C] + z)
+    check(lib().bq_re_gemm(handle(A.device.index or 0), ctypes.byref(Am), ctypes.byref(Bm),
+                           ctypes.byref(Cm), _stream(stream)))
+    return C
+
+
+def cx_gemm(A, B, C, opA="N", opB="N", stream=None):
+    """A, B, C: (re, im) pairs of real tensors."""
+    def pack(x):
+        return [x[0], None, None, None, x[1], None, None, None]
+    Am, Bm, Cm = matrix(pack(A)), matrix(pack(B)), matrix(pack(C))
+    check(lib().bq_cx_gemm(handle(A[0].device.index or 0), OPS[opA], OPS[opB], ctypes.byref(Am),
+                           ctypes.byref(Bm), ctypes.byref(Cm), _stream(stream)))
+    return C
+
+
+def rq_gemm(A, B, C, workspace=None, stream=None):
+    """A, B, C: lists of 4 real tensors (units 1, i, j, k)."""
+    import torch
+
+    def pack(x):
+        return list(x) + [None] * 4
+    Am, Bm, Cm = matrix(pack(A)), matrix(pack(B)), matrix(pack(C))
+    res, _ = workspace_size(Am.rows, Bm.cols, Am.cols, REAL_QUAT, REAL_QUAT)
+    if workspace is None:
+        workspace = torch.empty(max(res, 1), dtype=torch.uint8, device=A[0].device)
+    check(lib().bq_rq_gemm(handle(A[0].device.index or 0), ctypes.byref(Am), ctypes.byref(Bm),
+                           ctypes.byref(Cm), ctypes.c_void_p(workspace.data_ptr()),
+                           workspace.numel(), _stream(stream)))
+    return C

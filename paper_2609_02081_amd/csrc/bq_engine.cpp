@@ -1,0 +1,568 @@
+// Host engine of the bilinear biquaternion GEMM: argument validation (pure
+// host code, runs before anything is enqueued), planning (bilinear scheme of
+// eq. bilinearH or the component-wise form, whichever needs fewer real
+// GEMMs for the active components), workspace carving and kernel launches.
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bq.h"
+#include "bq_internal.h"
+
+struct bq_handle_s {
+  int device;
+  int cu_count;
+  std::string arch;
+};
+
+namespace {
+
+thread_local std::string g_detail = "no error";
+
+bq_status_t fail(bq_status_t s, const std::string& msg) {
+  g_detail = msg;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Quaternion unit algebra (Sec. II A): units 0..3 = 1, i, j, k with
+// i^2 = j^2 = k^2 = ijk = -1.  kUnitProd[u][v] = {sign, w}: e_u e_v = sign e_w.
+// ---------------------------------------------------------------------------
+struct UnitProd {
+  int sign;
+  int w;
+};
+constexpr UnitProd kUnitProd[4][4] = {
+    {{1, 0}, {1, 1}, {1, 2}, {1, 3}},
+    {{1, 1}, {-1, 0}, {1, 3}, {-1, 2}},
+    {{1, 2}, {-1, 3}, {-1, 0}, {1, 1}},
+    {{1, 3}, {1, 2}, {-1, 1}, {-1, 0}},
+};
+
+// eq. bilinearH: operand pairs (unit of M, unit of N) of P1..P4, their
+// weights in Q1..Q4, and the Hadamard rows of P5..P8.
+constexpr int kPairs[4][2] = {{0, 0}, {3, 2}, {1, 3}, {2, 1}};
+constexpr double kDirectCoef[4] = {2.0, -2.0, -2.0, -2.0};
+constexpr double kHad[4][4] = {{1, 1, 1, 1}, {1, 1, -1, -1}, {1, -1, 1, -1}, {1, -1, -1, 1}};
+// Q_w += kHadOut[w] * 1/4 * sum_q kHad[w][q] P_{5+q}
+constexpr double kHadOut[4] = {-0.25, 0.25, 0.25, 0.25};
+
+// Complex conjugation of an operand (Sec. III, sign rule for *): the unit
+// coefficient M_u becomes sgn[u] * conj(M_u).
+constexpr double kConjUnitSign[4] = {1.0, -1.0, 1.0, -1.0};
+
+struct Cplx {
+  double re, im;
+};
+inline Cplx cmul(Cplx a, Cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+struct Operand {
+  const double* r = nullptr;  // real part (nullptr = zero)
+  const double* i = nullptr;  // imaginary part (nullptr = zero)
+  int64_t ld = 0;
+  double s = 1.0;  // operand = r + i * s * i_part
+  int combo = -1;  // >= 0: Hadamard combination q, formed into the workspace
+};
+
+struct Tgt {
+  int w;
+  Cplx coef;
+};
+
+struct Prod {
+  Operand L, R;
+  std::vector<Tgt> tgts;
+};
+
+struct Plan {
+  bool bilinear = false;
+  std::vector<Prod> prods;
+  bool combA_r = false, combA_i = false, combB_r = false, combB_i = false;
+  double wA[4][4] = {}, wB[4][4] = {};
+  int real_gemms = 0;
+};
+
+int prod_cost(const Operand& L, const Operand& R) {
+  const int lparts = (L.r != nullptr) + (L.i != nullptr);
+  const int rparts = (R.r != nullptr) + (R.i != nullptr);
+  if (lparts == 0 || rparts == 0) return 0;
+  if (lparts == 2 && rparts == 2) return 3;
+  return lparts * rparts;
+}
+
+// Placeholder pointer marking "present, formed in the workspace".
+const double* const kCombo = reinterpret_cast<const double*>(uintptr_t(8));
+
+struct Problem {
+  int64_t m, n, k;
+  const double* a[8];
+  const double* b[8];
+  int64_t lda, ldb;
+  bool conjA, conjB;
+};
+
+Plan make_plan(const Problem& P) {
+  const double sA = P.conjA ? -1.0 : 1.0;
+  const double sB = P.conjB ? -1.0 : 1.0;
+  auto usA = [&](int u) { return P.conjA ? kConjUnitSign[u] : 1.0; };
+  auto usB = [&](int u) { return P.conjB ? kConjUnitSign[u] : 1.0; };
+
+  // Component-wise form: 16 complex products, absent ones skipped.
+  Plan cw;
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      Prod p;
+      p.L = {P.a[u], P.a[u + 4], P.lda, sA, -1};
+      p.R = {P.b[v], P.b[v + 4], P.ldb, sB, -1};
+      const int c = prod_cost(p.L, p.R);
+      if (c == 0) continue;
+      const UnitProd up = kUnitProd[u][v];
+      p.tgts.push_back({up.w, {up.sign * usA(u) * usB(v), 0.0}});
+      cw.real_gemms += c;
+      cw.prods.push_back(p);
+    }
+
+  // Bilinear form, eq. bilinearH.
+  Plan bl;
+  bl.bilinear = true;
+  for (int q = 0; q < 4; ++q) {
+    const int u = kPairs[q][0], v = kPairs[q][1];
+    Prod p;
+    p.L = {P.a[u], P.a[u + 4], P.lda, sA, -1};
+    p.R = {P.b[v], P.b[v + 4], P.ldb, sB, -1};
+    const int c = prod_cost(p.L, p.R);
+    if (c == 0) continue;
+    p.tgts.push_back({q, {kDirectCoef[q] * usA(u) * usB(v), 0.0}});
+    bl.real_gemms += c;
+    bl.prods.push_back(p);
+  }
+  bool aR = false, aI = false, bR = false, bI = false;
+  for (int u = 0; u < 4; ++u) {
+    aR |= P.a[u] != nullptr;
+    aI |= P.a[u + 4] != nullptr;
+    bR |= P.b[u] != nullptr;
+    bI |= P.b[u + 4] != nullptr;
+  }
+  for (int q = 0; q < 4; ++q) {
+    Prod p;
+    p.L = {aR ? kCombo : nullptr, aI ? kCombo : nullptr, 0, sA, q};
+    p.R = {bR ? kCombo : nullptr, bI ? kCombo : nullptr, 0, sB, q};
+    const int c = prod_cost(p.L, p.R);
+    if (c == 0) continue;
+    for (int w = 0; w < 4; ++w) p.tgts.push_back({w, {kHadOut[w] * kHad[w][q], 0.0}});
+    bl.real_gemms += c;
+    bl.prods.push_back(p);
+    for (int uu = 0; uu < 4; ++uu) {
+      bl.wA[q][uu] = kHad[q][uu] * usA(uu);
+      bl.wB[q][uu] = kHad[q][uu] * usB(uu);
+    }
+  }
+  bl.combA_r = aR;
+  bl.combA_i = aI;
+  bl.combB_r = bR;
+  bl.combB_i = bI;
+  if (bl.real_gemms <= cw.real_gemms) return bl;
+  return cw;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace: pre-combined operands of P5..P8 (packed, ld = cols).
+void workspace_need(const Plan& pl, int64_t m, int64_t n, int64_t k, size_t* resident, size_t* minimum) {
+  if (!pl.bilinear || m == 0 || n == 0 || k == 0) {
+    *resident = 0;
+    *minimum = 0;
+    return;
+  }
+  bool any = false;
+  for (const Prod& p : pl.prods) any |= (p.L.combo >= 0);
+  if (!any) {
+    *resident = 0;
+    *minimum = 0;
+    return;
+  }
+  const size_t a1 = align256(size_t(m) * size_t(k) * 8);
+  const size_t b1 = align256(size_t(k) * size_t(n) * 8);
+  const size_t per_q = (pl.combA_r + pl.combA_i) * a1 + (pl.combB_r + pl.combB_i) * b1;
+  *resident = 4 * per_q;
+  *minimum = per_q;
+}
+
+Problem problem_of(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B) {
+  Problem P;
+  P.m = A->rows;
+  P.k = A->cols;
+  P.n = B->cols;
+  for (int c = 0; c < 8; ++c) {
+    P.a[c] = A->comp[c];
+    P.b[c] = B->comp[c];
+  }
+  P.lda = A->ld;
+  P.ldb = B->ld;
+  P.conjA = (opA == BQ_OP_C);
+  P.conjB = (opB == BQ_OP_C);
+  return P;
+}
+
+struct Range {
+  uintptr_t lo, hi;
+};
+
+bool overlaps(Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; }
+
+Range block_range(const double* p, int64_t rows, int64_t cols, int64_t ld) {
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+  const uintptr_t bytes = (uintptr_t)(((rows - 1) * ld + cols) * 8);
+  return {lo, lo + bytes};
+}
+
+bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) != 0; }
+
+// Validation shared by every entry point.  out_mask: output components the
+// call writes (all of them must be non-null).
+bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                     const bq_matrix_t* C, bq_prec_t prec, int slices, const void* ws,
+                     size_t ws_bytes, unsigned out_mask, Plan* plan_out, bool* streamed) {
+  if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
+  auto op_ok = [](bq_op_t o) { return o == BQ_OP_N || o == BQ_OP_T || o == BQ_OP_C || o == BQ_OP_H; };
+  if (!op_ok(opA) || !op_ok(opB)) return fail(BQ_ERR_INVALID_VALUE, "op must be N, T, C or H");
+  if (prec != BQ_PREC_FP64 && prec != BQ_PREC_SPLIT_BF16 && prec != BQ_PREC_SPLIT_FP8)
+    return fail(BQ_ERR_INVALID_VALUE, "unknown precision");
+  if (slices < 0) return fail(BQ_ERR_INVALID_VALUE, "slices must be >= 0");
+  const bq_matrix_t* M[3] = {A, B, C};
+  const char* nm[3] = {"A", "B", "C"};
+  for (int t = 0; t < 3; ++t) {
+    if (M[t]->rows < 0 || M[t]->cols < 0)
+      return fail(BQ_ERR_INVALID_VALUE, std::string(nm[t]) + ": negative dimension");
+    if (M[t]->ld < std::max<int64_t>(1, M[t]->cols))
+      return fail(BQ_ERR_INVALID_VALUE, std::string(nm[t]) + ": ld < max(1, cols)");
+    for (int c = 0; c < 8; ++c)
+      if (M[t]->comp[c] && misaligned(M[t]->comp[c]))
+        return fail(BQ_ERR_INVALID_VALUE, std::string(nm[t]) + ": component not 8-byte aligned");
+  }
+  if (A->cols != B->rows) return fail(BQ_ERR_INVALID_VALUE, "A.cols != B.rows");
+  if (C->rows != A->rows || C->cols != B->cols)
+    return fail(BQ_ERR_INVALID_VALUE, "C must be A.rows x B.cols");
+  if (C->rows > 0 && C->cols > 0)
+    for (int c = 0; c < 8; ++c)
+      if ((out_mask >> c & 1) && !C->comp[c])
+        return fail(BQ_ERR_INVALID_VALUE, "output component " + std::to_string(c) + " is null");
+  if (opA == BQ_OP_T || opA == BQ_OP_H || opB == BQ_OP_T || opB == BQ_OP_H)
+    return fail(BQ_ERR_UNSUPPORTED, "op T and H are not implemented in this build");
+  if (prec != BQ_PREC_FP64) return fail(BQ_ERR_UNSUPPORTED, "split precision is not implemented in this build");
+  if (ws_bytes > 0 && !ws) return fail(BQ_ERR_INVALID_VALUE, "ws is null but ws_bytes > 0");
+
+  const int64_t m = A->rows, n = B->cols, k = A->cols;
+  Plan plan = make_plan(problem_of(opA, opB, A, B));
+  size_t res = 0, mn = 0;
+  workspace_need(plan, m, n, k, &res, &mn);
+  if (ws_bytes < mn)
+    return fail(BQ_ERR_WORKSPACE, "workspace " + std::to_string(ws_bytes) + " B < minimum " + std::to_string(mn) + " B");
+  const char* fs = std::getenv("BQ_FORCE_STREAMED");
+  const bool force_stream = fs && fs[0] == '1';
+  const bool use_stream = (ws_bytes < res) || (force_stream && mn < res);
+
+  // Aliasing: output blocks against inputs, workspace and each other.
+  if (m > 0 && n > 0) {
+    std::vector<Range> outs;
+    for (int c = 0; c < 8; ++c)
+      if (out_mask >> c & 1) outs.push_back(block_range(C->comp[c], m, n, C->ld));
+    std::vector<Range> ins;
+    if (k > 0) {
+      for (int c = 0; c < 8; ++c) {
+        if (A->comp[c]) ins.push_back(block_range(A->comp[c], m, k, A->ld));
+        if (B->comp[c]) ins.push_back(block_range(B->comp[c], k, n, B->ld));
+      }
+    }
+    const size_t used_ws = use_stream ? mn : res;
+    if (ws && used_ws > 0) {
+      const uintptr_t lo = reinterpret_cast<uintptr_t>(ws);
+      ins.push_back({lo, lo + used_ws});
+    }
+    for (size_t i = 0; i < outs.size(); ++i) {
+      for (const Range& r : ins)
+        if (overlaps(outs[i], r)) return fail(BQ_ERR_ALIAS, "C overlaps an input or the workspace");
+      for (size_t j = i + 1; j < outs.size(); ++j)
+        if (overlaps(outs[i], outs[j])) return fail(BQ_ERR_ALIAS, "two components of C overlap");
+    }
+  }
+  if (plan_out) *plan_out = std::move(plan);
+  if (streamed) *streamed = use_stream;
+  return BQ_OK;
+}
+
+int tile_override() {
+  const char* e = std::getenv("BQ_TILE_CONFIG");
+  if (!e || !*e) return -1;
+  const int v = std::atoi(e);
+  return (v >= 0 && v < bq::num_tile_configs()) ? v : -1;
+}
+
+bq_status_t hip_fail(hipError_t e, const char* what) {
+  return fail(BQ_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Enqueue the plan.  Validation has passed.
+bq_status_t execute(const Plan& pl, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C,
+                    unsigned out_mask, void* ws, bool streamed, hipStream_t s) {
+  const int64_t m = A->rows, n = B->cols, k = A->cols;
+  if (m == 0 || n == 0) return BQ_OK;
+  bool touched[8] = {};
+  const int cfg_override = tile_override();
+
+  // Workspace slots for the pre-combined operands.
+  const size_t a1 = align256(size_t(m) * size_t(k) * 8);
+  const size_t b1 = align256(size_t(k) * size_t(n) * 8);
+  char* wp = static_cast<char*>(ws);
+  double* cA_r[4] = {};
+  double* cA_i[4] = {};
+  double* cB_r[4] = {};
+  double* cB_i[4] = {};
+  const int nslot = streamed ? 1 : 4;
+  for (int q = 0; q < nslot && k > 0; ++q) {
+    if (pl.combA_r) { cA_r[q] = reinterpret_cast<double*>(wp); wp += a1; }
+    if (pl.combA_i) { cA_i[q] = reinterpret_cast<double*>(wp); wp += a1; }
+    if (pl.combB_r) { cB_r[q] = reinterpret_cast<double*>(wp); wp += b1; }
+    if (pl.combB_i) { cB_i[q] = reinterpret_cast<double*>(wp); wp += b1; }
+  }
+
+  auto combine = [&](bool left, int q0, int nq, int slot0) -> hipError_t {
+    bq::CombineArgs ca{};
+    const bq_matrix_t* X = left ? A : B;
+    for (int c = 0; c < 8; ++c) ca.src[c] = X->comp[c];
+    ca.lds = X->ld;
+    ca.rows = left ? m : k;
+    ca.cols = left ? k : n;
+    ca.ldd = ca.cols;
+    ca.nq = nq;
+    for (int j = 0; j < nq; ++j) {
+      ca.dst_r[j] = left ? cA_r[slot0 + j] : cB_r[slot0 + j];
+      ca.dst_i[j] = left ? cA_i[slot0 + j] : cB_i[slot0 + j];
+      for (int u = 0; u < 4; ++u) ca.w[j][u] = left ? pl.wA[q0 + j][u] : pl.wB[q0 + j][u];
+    }
+    return bq::launch_combine(ca, s);
+  };
+
+  if (k > 0 && pl.bilinear && !streamed) {
+    hipError_t e = combine(true, 0, 4, 0);
+    if (e == hipSuccess) e = combine(false, 0, 4, 0);
+    if (e != hipSuccess) return hip_fail(e, "pre-combination launch");
+  }
+
+  for (const Prod& p : pl.prods) {
+    if (k == 0) break;
+    Operand L = p.L, R = p.R;
+    if (L.combo >= 0) {
+      const int slot = streamed ? 0 : L.combo;
+      if (streamed) {
+        hipError_t e = combine(true, L.combo, 1, 0);
+        if (e == hipSuccess) e = combine(false, R.combo, 1, 0);
+        if (e != hipSuccess) return hip_fail(e, "pre-combination launch");
+      }
+      L.r = L.r ? cA_r[slot] : nullptr;
+      L.i = L.i ? cA_i[slot] : nullptr;
+      L.ld = k;
+      R.r = R.r ? cB_r[slot] : nullptr;
+      R.i = R.i ? cB_i[slot] : nullptr;
+      R.ld = n;
+    }
+    // Imaginary-only operands: (i s x) as a real operand x times i s.
+    Cplx rot = {1.0, 0.0};
+    if (!L.r && L.i) { rot = cmul(rot, {0.0, L.s}); L.r = L.i; L.i = nullptr; }
+    if (!R.r && R.i) { rot = cmul(rot, {0.0, R.s}); R.r = R.i; R.i = nullptr; }
+    int kind;
+    if (L.i && R.i) kind = bq::KIND_GAUSS;
+    else if (R.i) kind = bq::KIND_RC;
+    else if (L.i) kind = bq::KIND_CR;
+    else kind = bq::KIND_RR;
+    const bool pr_nz = true;
+    const bool pi_nz = (kind != bq::KIND_RR);
+
+    bq::GemmArgs g{};
+    g.lr = L.r; g.li = L.i; g.lda = L.ld;
+    g.rr = R.r; g.ri = R.i; g.ldb = R.ld;
+    g.m = m; g.n = n; g.k = k;
+    g.sL = L.s; g.sR = R.s;
+    g.ldc = C->ld;
+    g.ntgt = 0;
+    for (const Tgt& t : p.tgts) {
+      const Cplx c = cmul(t.coef, rot);
+      const bool out_r = (c.re != 0.0 && pr_nz) || (c.im != 0.0 && pi_nz);
+      const bool out_i = (c.re != 0.0 && pi_nz) || (c.im != 0.0 && pr_nz);
+      bq::Target T{};
+      T.ar = c.re;
+      T.ai = c.im;
+      T.cr = C->comp[t.w];
+      T.ci = C->comp[t.w + 4];
+      const bool want_r = out_r && (out_mask >> t.w & 1);
+      const bool want_i = out_i && (out_mask >> (t.w + 4) & 1);
+      T.mode_r = want_r ? (touched[t.w] ? bq::TGT_ACCUM : bq::TGT_WRITE) : bq::TGT_SKIP;
+      T.mode_i = want_i ? (touched[t.w + 4] ? bq::TGT_ACCUM : bq::TGT_WRITE) : bq::TGT_SKIP;
+      if (want_r) touched[t.w] = true;
+      if (want_i) touched[t.w + 4] = true;
+      if (T.mode_r == bq::TGT_SKIP && T.mode_i == bq::TGT_SKIP) continue;
+      g.tgt[g.ntgt++] = T;
+    }
+    if (g.ntgt == 0) continue;
+    const int cfg = cfg_override >= 0 ? cfg_override : bq::default_tile_config(kind, m, n, k);
+    hipError_t e = bq::launch_cgemm(kind, g, cfg, s);
+    if (e != hipSuccess) return hip_fail(e, "GEMM launch");
+  }
+  for (int c = 0; c < 8; ++c) {
+    if ((out_mask >> c & 1) && !touched[c]) {
+      hipError_t e = bq::launch_fill_zero(C->comp[c], m, n, C->ld, s);
+      if (e != hipSuccess) return hip_fail(e, "zero-fill launch");
+    }
+  }
+  return BQ_OK;
+}
+
+bq_status_t check_handle(bq_handle_t h) {
+  if (!h) return fail(BQ_ERR_INVALID_VALUE, "handle is null");
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != h->device) {
+    e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  }
+  return BQ_OK;
+}
+
+bq_status_t run(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                bq_matrix_t* C, bq_prec_t prec, int slices, void* ws, size_t ws_bytes, unsigned out_mask,
+                bq_stream_t stream) {
+  if (!h) return fail(BQ_ERR_INVALID_VALUE, "handle is null");
+  Plan plan;
+  bool streamed = false;
+  bq_status_t st = validate(opA, opB, A, B, C, prec, slices, ws, ws_bytes, out_mask, &plan, &streamed);
+  if (st != BQ_OK) return st;
+  st = check_handle(h);
+  if (st != BQ_OK) return st;
+  return execute(plan, A, B, C, out_mask, ws, streamed, static_cast<hipStream_t>(stream));
+}
+
+bq_matrix_t restrict_to(const bq_matrix_t* X, unsigned mask) {
+  bq_matrix_t Y = *X;
+  for (int c = 0; c < 8; ++c)
+    if (!(mask >> c & 1)) Y.comp[c] = nullptr;
+  return Y;
+}
+
+}  // namespace
+
+extern "C" {
+
+bq_status_t bq_create(bq_handle_t* h, int device) {
+  if (!h) return fail(BQ_ERR_INVALID_VALUE, "h is null");
+  *h = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= count) return fail(BQ_ERR_INVALID_VALUE, "device out of range");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BQ_ERR_ARCH, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  bq_handle_s* hh = new bq_handle_s;
+  hh->device = device;
+  hh->cu_count = prop.multiProcessorCount;
+  hh->arch = prop.gcnArchName;
+  *h = hh;
+  return BQ_OK;
+}
+
+bq_status_t bq_destroy(bq_handle_t h) {
+  delete h;
+  return BQ_OK;
+}
+
+const char* bq_status_string(bq_status_t s) {
+  switch (s) {
+    case BQ_OK: return "BQ_OK";
+    case BQ_ERR_INVALID_VALUE: return "BQ_ERR_INVALID_VALUE";
+    case BQ_ERR_UNSUPPORTED: return "BQ_ERR_UNSUPPORTED";
+    case BQ_ERR_ALIAS: return "BQ_ERR_ALIAS";
+    case BQ_ERR_WORKSPACE: return "BQ_ERR_WORKSPACE";
+    case BQ_ERR_HIP: return "BQ_ERR_HIP";
+    case BQ_ERR_ARCH: return "BQ_ERR_ARCH";
+  }
+  return "BQ_ERR_UNKNOWN";
+}
+
+const char* bq_last_error_detail(void) { return g_detail.c_str(); }
+
+bq_status_t bq_gemm_workspace_size(int64_t m, int64_t n, int64_t k, unsigned maskA, unsigned maskB,
+                                   bq_prec_t prec, int slices, size_t* resident_bytes, size_t* min_bytes) {
+  if (m < 0 || n < 0 || k < 0) return fail(BQ_ERR_INVALID_VALUE, "negative dimension");
+  if (maskA > 0xFFu || maskB > 0xFFu) return fail(BQ_ERR_INVALID_VALUE, "mask has bits above 7");
+  if (prec != BQ_PREC_FP64 && prec != BQ_PREC_SPLIT_BF16 && prec != BQ_PREC_SPLIT_FP8)
+    return fail(BQ_ERR_INVALID_VALUE, "unknown precision");
+  if (slices < 0) return fail(BQ_ERR_INVALID_VALUE, "slices must be >= 0");
+  Problem P{};
+  P.m = m; P.n = n; P.k = k;
+  const double* present = kCombo;
+  for (int c = 0; c < 8; ++c) {
+    P.a[c] = (maskA >> c & 1) ? present : nullptr;
+    P.b[c] = (maskB >> c & 1) ? present : nullptr;
+  }
+  P.lda = std::max<int64_t>(1, k);
+  P.ldb = std::max<int64_t>(1, n);
+  Plan pl = make_plan(P);
+  size_t res = 0, mn = 0;
+  workspace_need(pl, m, n, k, &res, &mn);
+  if (resident_bytes) *resident_bytes = res;
+  if (min_bytes) *min_bytes = mn;
+  return BQ_OK;
+}
+
+int bq_plan_real_gemms(unsigned maskA, unsigned maskB) {
+  Problem P{};
+  P.m = P.n = P.k = 1;
+  for (int c = 0; c < 8; ++c) {
+    P.a[c] = (maskA >> c & 1) ? kCombo : nullptr;
+    P.b[c] = (maskB >> c & 1) ? kCombo : nullptr;
+  }
+  P.lda = P.ldb = 1;
+  return make_plan(P).real_gemms;
+}
+
+bq_status_t bq_gemm_check(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                          const bq_matrix_t* C, bq_prec_t prec, int slices, const void* ws, size_t ws_bytes) {
+  return validate(opA, opB, A, B, C, prec, slices, ws, ws_bytes, 0xFFu, nullptr, nullptr);
+}
+
+bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                    bq_matrix_t* C, bq_prec_t prec, int slices, void* ws, size_t ws_bytes, bq_stream_t stream) {
+  return run(h, opA, opB, A, B, C, prec, slices, ws, ws_bytes, 0xFFu, stream);
+}
+
+bq_status_t bq_re_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C,
+                       bq_stream_t stream) {
+  if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
+  bq_matrix_t a = restrict_to(A, BQ_MASK_REAL), b = restrict_to(B, BQ_MASK_REAL), c = restrict_to(C, BQ_MASK_REAL);
+  if (!a.comp[0] || !b.comp[0]) return fail(BQ_ERR_INVALID_VALUE, "bq_re_gemm needs comp[0] of A and B");
+  return run(h, BQ_OP_N, BQ_OP_N, &a, &b, &c, BQ_PREC_FP64, 0, nullptr, 0, BQ_MASK_REAL, stream);
+}
+
+bq_status_t bq_cx_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                       bq_matrix_t* C, bq_stream_t stream) {
+  if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
+  bq_matrix_t a = restrict_to(A, BQ_MASK_COMPLEX), b = restrict_to(B, BQ_MASK_COMPLEX),
+              c = restrict_to(C, BQ_MASK_COMPLEX);
+  return run(h, opA, opB, &a, &b, &c, BQ_PREC_FP64, 0, nullptr, 0, BQ_MASK_COMPLEX, stream);
+}
+
+bq_status_t bq_rq_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C, void* ws,
+                       size_t ws_bytes, bq_stream_t stream) {
+  if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
+  bq_matrix_t a = restrict_to(A, BQ_MASK_REAL_QUATERNION), b = restrict_to(B, BQ_MASK_REAL_QUATERNION),
+              c = restrict_to(C, BQ_MASK_REAL_QUATERNION);
+  return run(h, BQ_OP_N, BQ_OP_N, &a, &b, &c, BQ_PREC_FP64, 0, ws, ws_bytes, BQ_MASK_REAL_QUATERNION, stream);
+}
+
+}  // extern "C"

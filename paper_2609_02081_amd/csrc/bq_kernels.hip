@@ -1,0 +1,398 @@
+// gfx950 (CDNA4) kernels of the bilinear biquaternion GEMM.
+//
+//  cgemm_f64   One complex product P = L.R of eq. bilinearH as FP64 MFMA
+//              real GEMMs (v_mfma_f64_16x16x4f64), Gauss-fused: one tile
+//              keeps T1, T2, T3 of eq. cmplx-3-real-mult in three
+//              accumulator sets, forms the sums lr+li / rr+ri on the MFMA
+//              fragments in registers, and the epilogue turns (T1,T2,T3)
+//              into P and adds coef*P straight into the C blocks (the
+//              post-combination of eq. bilinearH), so neither the Gauss sums
+//              nor T or P ever reach HBM.
+//  combine     Hadamard pre-combinations (M1 +- M2 +- M3 +- M4) of
+//              eq. bilinearH, HBM-bound.
+//  fill_zero   Structurally zero output blocks.
+//
+// Tile base pointers are 64-bit; offsets inside a tile are 32-bit.  Build with
+//   -Xclang -target-feature -Xclang -packed-fp32-ops
+#include "bq_internal.h"
+
+namespace bq {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// Tile order: workgroups are dealt to the 8 XCDs round-robin (w % 8).  Give
+// every XCD a contiguous range of logical tiles, and walk that range in
+// groups of GROUP_M tile-rows so tiles that run together share A and B panels
+// in their XCD's L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
+  constexpr int kXcd = 8;
+  constexpr int kGroupM = 8;
+  const int T = tiles_m * tiles_n;
+  const int w = blockIdx.x;
+  const int x = w % kXcd, slot = w / kXcd;
+  const int base = T / kXcd, rem = T % kXcd;
+  const int t = x * base + (x < rem ? x : rem) + slot;
+  const int per_group = kGroupM * tiles_n;
+  const int group = t / per_group;
+  const int first_m = group * kGroupM;
+  const int gm = min(tiles_m - first_m, kGroupM);
+  const int in_g = t - group * per_group;
+  tm = first_m + in_g % gm;
+  tn = in_g / gm;
+}
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA complex-product GEMM.
+//
+// Fragment layout of v_mfma_f64_16x16x4f64 (wave64):
+//   A (16x4):  lane l holds A[l % 16][l / 16]
+//   B (4x16):  lane l holds B[l / 16][l % 16]
+//   D (16x16): lane l, element v holds D[l / 16 + 4 v][l % 16]
+// (the D layout was checked on gfx950 with a one-wave probe).
+// LDS keeps the A tile k-major (As[k][i]) and the B tile as stored
+// (Bs[k][j]) so both fragment reads are 16 consecutive doubles per k row.
+// ---------------------------------------------------------------------------
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+__attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+cgemm_f64(const GemmArgs g) {
+  constexpr int NWN = BN / WN;
+  constexpr int NT = (BM / WM) * NWN * 64;
+  constexpr int MI = WM / 16, NI = WN / 16;
+  constexpr bool HAS_LI = (KIND == KIND_GAUSS || KIND == KIND_CR);
+  constexpr bool HAS_RI = (KIND == KIND_GAUSS || KIND == KIND_RC);
+  constexpr int NA = HAS_LI ? 2 : 1;
+  constexpr int NB = HAS_RI ? 2 : 1;
+  constexpr int NACC = KIND == KIND_GAUSS ? 3 : (KIND == KIND_RR ? 1 : 2);
+  constexpr int PAD = 4;
+  constexpr int A_PER = BM * BK / NT;
+  constexpr int B_PER = BK * BN / NT;
+  static_assert(A_PER * NT == BM * BK && B_PER * NT == BK * BN, "tile / thread mismatch");
+  static_assert(BK % 4 == 0 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
+
+  __shared__ double As[NA][BK][BM + PAD];
+  __shared__ double Bs[NB][BK][BN + PAD];
+
+  const int tiles_m = (int)((g.m + BM - 1) / BM);
+  const int tiles_n = (int)((g.n + BN - 1) / BN);
+  int tm, tn;
+  tile_coords(tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM;
+  const int64_t n0 = (int64_t)tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / NWN) * WM;
+  const int wn0 = (wave % NWN) * WN;
+  const int fr = lane & 15;
+  const int fk = lane >> 4;
+
+  // Per-tile base pointers: all further offsets stay small.
+  const double* pa[2] = {g.lr + m0 * g.lda, HAS_LI ? g.li + m0 * g.lda : nullptr};
+  const double* pb[2] = {g.rr + n0, HAS_RI ? g.ri + n0 : nullptr};
+  const int64_t mrem = g.m - m0;
+  const int64_t nrem = g.n - n0;
+
+  double ra[NA][A_PER];
+  double rb[NB][B_PER];
+
+  // Per-thread element offsets inside a K-tile: fixed for the whole loop,
+  // 32-bit (the host guarantees BM * lda and BK * ldb fit).
+  uint32_t offA[A_PER], offB[B_PER];
+  uint32_t okA = 0, okB = 0;  // row / column inside the matrix, per element
+#pragma unroll
+  for (int i = 0; i < A_PER; ++i) {
+    const int e = tid + i * NT;
+    const int r = e / BK, c = e % BK;
+    offA[i] = (uint32_t)r * (uint32_t)g.lda + (uint32_t)c;
+    okA |= (uint32_t)(r < mrem) << i;
+  }
+#pragma unroll
+  for (int i = 0; i < B_PER; ++i) {
+    const int e = tid + i * NT;
+    const int r = e / BN, c = e % BN;
+    offB[i] = (uint32_t)r * (uint32_t)g.ldb + (uint32_t)c;
+    okB |= (uint32_t)(c < nrem) << i;
+  }
+
+  auto gload = [&](int64_t k0) {
+    const bool kfull = (k0 + BK <= g.k);
+    const int64_t kleft = g.k - k0;
+#pragma unroll
+    for (int p = 0; p < NA; ++p) {
+      const double* base = pa[p] + k0;
+#pragma unroll
+      for (int i = 0; i < A_PER; ++i) {
+        const int c = (tid + i * NT) % BK;
+        const bool ok = ((okA >> i) & 1) && (kfull || c < kleft);
+        ra[p][i] = ok ? base[offA[i]] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+      const double* base = pb[p] + k0 * g.ldb;
+#pragma unroll
+      for (int i = 0; i < B_PER; ++i) {
+        const int r = (tid + i * NT) / BN;
+        const bool ok = ((okB >> i) & 1) && (kfull || r < kleft);
+        rb[p][i] = ok ? base[offB[i]] : 0.0;
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int e = tid + i * NT;
+      const int r = e / BK, c = e % BK;
+#pragma unroll
+      for (int p = 0; p < NA; ++p) As[p][c][r] = ra[p][i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int e = tid + i * NT;
+      const int r = e / BN, c = e % BN;
+#pragma unroll
+      for (int p = 0; p < NB; ++p) Bs[p][r][c] = rb[p][i];
+    }
+  };
+
+  d4 acc[NACC][MI][NI];
+#pragma unroll
+  for (int q = 0; q < NACC; ++q)
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) acc[q][i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const double sL = g.sL, sR = g.sR;
+  const int64_t nk = (g.k + BK - 1) / BK;
+  if (nk > 0) gload(0);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    lstore();
+    __syncthreads();
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int krow = kk * 4 + fk;
+      double a[NA][MI], b[NB][NI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int p = 0; p < NA; ++p) a[p][i] = As[p][krow][wm0 + i * 16 + fr];
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+#pragma unroll
+        for (int p = 0; p < NB; ++p) b[p][j] = Bs[p][krow][wn0 + j * 16 + fr];
+      if constexpr (KIND == KIND_GAUSS) {
+        double as[MI], bs[NI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) as[i] = __builtin_fma(sL, a[HAS_LI ? 1 : 0][i], a[0][i]);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) bs[j] = __builtin_fma(sR, b[HAS_RI ? 1 : 0][j], b[0][j]);
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j) {
+            acc[0][i][j] = mfma_f64(a[0][i], b[0][j], acc[0][i][j]);
+            acc[1][i][j] = mfma_f64(a[HAS_LI ? 1 : 0][i], b[HAS_RI ? 1 : 0][j], acc[1 % NACC][i][j]);
+            acc[2 % NACC][i][j] = mfma_f64(as[i], bs[j], acc[2 % NACC][i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j) {
+            acc[0][i][j] = mfma_f64(a[0][i], b[0][j], acc[0][i][j]);
+            if constexpr (KIND == KIND_RC)
+              acc[1 % NACC][i][j] = mfma_f64(a[0][i], b[NB - 1][j], acc[1 % NACC][i][j]);
+            if constexpr (KIND == KIND_CR)
+              acc[1 % NACC][i][j] = mfma_f64(a[NA - 1][i], b[0][j], acc[1 % NACC][i][j]);
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: P from the accumulators, then coef * P into each target.
+  const int64_t ldc = g.ldc;
+  const double sig = sL * sR;
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = wm0 + i * 16 + fk + 4 * v;
+        const int64_t c = wn0 + j * 16 + fr;
+        if (r >= mrem || c >= nrem) continue;
+        double pr, pi;
+        if constexpr (KIND == KIND_GAUSS) {
+          const double t1 = acc[0][i][j][v];
+          const double t2 = acc[1][i][j][v];
+          const double t3 = acc[2 % NACC][i][j][v];
+          pr = t1 - sig * t2;
+          pi = (t3 - t1) - sig * t2;
+        } else if constexpr (KIND == KIND_RC) {
+          pr = acc[0][i][j][v];
+          pi = sR * acc[1 % NACC][i][j][v];
+        } else if constexpr (KIND == KIND_CR) {
+          pr = acc[0][i][j][v];
+          pi = sL * acc[1 % NACC][i][j][v];
+        } else {
+          pr = acc[0][i][j][v];
+          pi = 0.0;
+        }
+        const int64_t off = (m0 + r) * ldc + n0 + c;
+        for (int t = 0; t < g.ntgt; ++t) {
+          const Target& T = g.tgt[t];
+          if (T.mode_r != TGT_SKIP) {
+            double val = (T.ai == 0.0) ? T.ar * pr : ((T.ar == 0.0) ? -T.ai * pi : T.ar * pr - T.ai * pi);
+            if (T.mode_r == TGT_ACCUM) val += T.cr[off];
+            T.cr[off] = val;
+          }
+          if (T.mode_i != TGT_SKIP) {
+            double val = (T.ai == 0.0) ? T.ar * pi : ((T.ar == 0.0) ? T.ai * pr : T.ar * pi + T.ai * pr);
+            if (T.mode_i == TGT_ACCUM) val += T.ci[off];
+            T.ci[off] = val;
+          }
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Hadamard pre-combination.  One thread produces two adjacent columns of
+// every requested combination.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) combine_kernel(const CombineArgs a) {
+  const int64_t cpairs = (a.cols + 1) / 2;
+  const int64_t bpr = (cpairs + 255) / 256;
+  const int64_t row = blockIdx.x / bpr;
+  const int64_t c = ((blockIdx.x % bpr) * 256 + threadIdx.x) * 2;
+  if (row >= a.rows || c >= a.cols) return;
+  const bool two = (c + 1 < a.cols);
+  double x[8][2];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const double* s = a.src[u];
+    if (s) {
+      const double* p = s + row * a.lds + c;
+      x[u][0] = p[0];
+      x[u][1] = two ? p[1] : 0.0;
+    } else {
+      x[u][0] = 0.0;
+      x[u][1] = 0.0;
+    }
+  }
+  for (int q = 0; q < a.nq; ++q) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double* d = (h == 0) ? a.dst_r[q] : a.dst_i[q];
+      if (!d) continue;
+      const int o = 4 * h;
+      double v0 = a.w[q][0] * x[o][0];
+      double v1 = a.w[q][0] * x[o][1];
+#pragma unroll
+      for (int u = 1; u < 4; ++u) {
+        v0 = v0 + a.w[q][u] * x[o + u][0];
+        v1 = v1 + a.w[q][u] * x[o + u][1];
+      }
+      double* p = d + row * a.ldd + c;
+      p[0] = v0;
+      if (two) p[1] = v1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t bpr = (cols + 255) / 256;
+  const int64_t row = blockIdx.x / bpr;
+  const int64_t c = (blockIdx.x % bpr) * 256 + threadIdx.x;
+  if (row < rows && c < cols) p[row * ld + c] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Tile configurations and launchers.
+// ---------------------------------------------------------------------------
+static const TileConfig kConfigs[] = {
+    {64, 64, 16, 32, 32},    // 0: 4 waves, 2 waves / SIMD
+    {64, 64, 16, 32, 32},    // 1: 4 waves, 1 wave / SIMD
+    {128, 64, 16, 64, 32},   // 2: 4 waves, 1 wave / SIMD
+    {64, 64, 32, 32, 32},    // 3: 4 waves, 2 waves / SIMD
+    {128, 128, 8, 64, 32},   // 4: 8 waves, 2 waves / SIMD
+    {128, 128, 16, 64, 64},  // 5: 4 waves, 1 wave / SIMD
+    {64, 64, 8, 32, 32},     // 6: 4 waves, 2 waves / SIMD
+};
+constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
+
+int num_tile_configs() { return kNumConfigs; }
+TileConfig tile_config(int cfg) { return kConfigs[cfg]; }
+
+int default_tile_config(int kind, int64_t m, int64_t n, int64_t k) {
+  (void)k;
+  (void)m;
+  (void)n;
+  (void)kind;
+  return 0;
+}
+
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE>
+static hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
+  const int64_t tm = (g.m + BM - 1) / BM, tn = (g.n + BN - 1) / BN;
+  const int64_t tiles = tm * tn;
+  if (tiles <= 0) return hipSuccess;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  constexpr int NT = (BM / WM) * (BN / WN) * 64;
+  hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE>), dim3((unsigned)tiles), dim3(NT), 0, s, g);
+  return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t launch_kind(const GemmArgs& g, int cfg, hipStream_t s) {
+  switch (cfg) {
+    case 0: return launch_one<KIND, 64, 64, 16, 32, 32, 2>(g, s);
+    case 1: return launch_one<KIND, 64, 64, 16, 32, 32, 1>(g, s);
+    case 2: return launch_one<KIND, 128, 64, 16, 64, 32, 1>(g, s);
+    case 3: return launch_one<KIND, 64, 64, 32, 32, 32, 2>(g, s);
+    case 4: return launch_one<KIND, 128, 128, 8, 64, 32, 2>(g, s);
+    case 5: return launch_one<KIND, 128, 128, 16, 64, 64, 1>(g, s);
+    case 6: return launch_one<KIND, 64, 64, 8, 32, 32, 2>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cgemm(int kind, const GemmArgs& g, int cfg, hipStream_t s) {
+  switch (kind) {
+    case KIND_GAUSS: return launch_kind<KIND_GAUSS>(g, cfg, s);
+    case KIND_RC: return launch_kind<KIND_RC>(g, cfg, s);
+    case KIND_CR: return launch_kind<KIND_CR>(g, cfg, s);
+    case KIND_RR: return launch_kind<KIND_RR>(g, cfg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_combine(const CombineArgs& a, hipStream_t s) {
+  if (a.rows <= 0 || a.cols <= 0) return hipSuccess;
+  const int64_t bpr = ((a.cols + 1) / 2 + 255) / 256;
+  const int64_t blocks = bpr * a.rows;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t blocks = ((cols + 255) / 256) * rows;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, rows, cols, ld);
+  return hipGetLastError();
+}
+
+}  // namespace bq

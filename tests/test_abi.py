@@ -1,0 +1,157 @@
+"""C-ABI contract, host only: the library loads, exports every symbol the
+header declares, and every argument error is caught before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2609_02081_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bq.h")
+
+OK, INVALID, UNSUPPORTED, ALIAS, WORKSPACE, HIP, ARCH = range(7)
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bq_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = B.lib()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert sorted(n for n, _, _ in B._SIGS) == names
+
+
+def test_status_strings():
+    lib = B.lib()
+    for code, name in B.STATUS.items():
+        assert lib.bq_status_string(code).decode() == name
+    assert lib.bq_status_string(99).decode() == "BQ_ERR_UNKNOWN"
+
+
+FAKE = 1 << 40  # host integers standing in for device addresses; never dereferenced
+
+
+def mat(rows, cols, base, ld=None, mask=0xFF, stride=None):
+    M = B.BqMatrix()
+    ld = ld if ld is not None else max(1, cols)
+    stride = stride if stride is not None else ((rows * ld + 31) // 32 * 32) * 8
+    for c in range(8):
+        M.comp[c] = (base + c * stride) if (mask >> c & 1) else None
+    M.rows, M.cols, M.ld = rows, cols, ld
+    return M
+
+
+def check(A, Bm, C, opA=0, opB=0, prec=0, slices=0, ws=None, ws_bytes=0):
+    return B.lib().bq_gemm_check(opA, opB, ctypes.byref(A), ctypes.byref(Bm), ctypes.byref(C), prec,
+                                 slices, ws, ws_bytes)
+
+
+def ws_need(m, n, k, ma=0xFF, mb=0xFF):
+    return B.workspace_size(m, n, k, ma, mb)
+
+
+def test_valid_call_passes():
+    m, n, k = 40, 30, 20
+    res, mn = ws_need(m, n, k)
+    assert check(mat(m, k, FAKE), mat(k, n, 2 * FAKE), mat(m, n, 3 * FAKE), ws=4 * FAKE,
+                 ws_bytes=res) == OK
+    assert check(mat(m, k, FAKE), mat(k, n, 2 * FAKE), mat(m, n, 3 * FAKE), ws=4 * FAKE,
+                 ws_bytes=mn) == OK   # streamed plan
+
+
+def test_null_arguments():
+    lib = B.lib()
+    A, Bm, C = mat(4, 4, FAKE), mat(4, 4, 2 * FAKE), mat(4, 4, 3 * FAKE)
+    assert lib.bq_gemm_check(0, 0, None, ctypes.byref(Bm), ctypes.byref(C), 0, 0, None, 0) == INVALID
+    C.comp[5] = None
+    assert check(A, Bm, C, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
+    assert "output component 5" in B.last_error()
+    assert lib.bq_gemm(None, 0, 0, ctypes.byref(A), ctypes.byref(Bm), ctypes.byref(C), 0, 0, None, 0,
+                       None) == INVALID
+
+
+def test_shapes_and_leading_dimensions():
+    ws = (4 * FAKE, 1 << 30)
+    assert check(mat(4, 5, FAKE), mat(6, 3, 2 * FAKE), mat(4, 3, 3 * FAKE), ws=ws[0], ws_bytes=ws[1]) == INVALID
+    assert check(mat(4, 5, FAKE), mat(5, 3, 2 * FAKE), mat(4, 4, 3 * FAKE), ws=ws[0], ws_bytes=ws[1]) == INVALID
+    assert check(mat(4, 5, FAKE, ld=4), mat(5, 3, 2 * FAKE), mat(4, 3, 3 * FAKE), ws=ws[0],
+                 ws_bytes=ws[1]) == INVALID
+    bad = mat(4, 5, FAKE)
+    bad.rows = -1
+    assert check(bad, mat(5, 3, 2 * FAKE), mat(4, 3, 3 * FAKE), ws=ws[0], ws_bytes=ws[1]) == INVALID
+    mis = mat(4, 5, FAKE + 4)
+    assert check(mis, mat(5, 3, 2 * FAKE), mat(4, 3, 3 * FAKE), ws=ws[0], ws_bytes=ws[1]) == INVALID
+
+
+def test_unsupported_ops_and_precisions():
+    A, Bm, C = mat(4, 4, FAKE), mat(4, 4, 2 * FAKE), mat(4, 4, 3 * FAKE)
+    for op in (1, 3):
+        assert check(A, Bm, C, opA=op, ws=4 * FAKE, ws_bytes=1 << 30) == UNSUPPORTED
+        assert check(A, Bm, C, opB=op, ws=4 * FAKE, ws_bytes=1 << 30) == UNSUPPORTED
+    assert check(A, Bm, C, opA=7) == INVALID
+    assert check(A, Bm, C, prec=9) == INVALID
+    assert check(A, Bm, C, slices=-1) == INVALID
+
+
+def test_alias_detection():
+    m = n = k = 16
+    res, _ = ws_need(m, n, k)
+    A = mat(m, k, FAKE)
+    # C overlapping A
+    assert check(A, mat(k, n, 2 * FAKE), mat(m, n, FAKE + 8 * 100), ws=4 * FAKE, ws_bytes=res) == ALIAS
+    # C overlapping the workspace
+    assert check(A, mat(k, n, 2 * FAKE), mat(m, n, 4 * FAKE + 64), ws=4 * FAKE, ws_bytes=res) == ALIAS
+    # two components of C overlapping each other
+    assert check(A, mat(k, n, 2 * FAKE), mat(m, n, 3 * FAKE, stride=64), ws=4 * FAKE,
+                 ws_bytes=res) == ALIAS
+
+
+def test_workspace_sizes_and_errors():
+    m, n, k = 100, 60, 40
+    res, mn = ws_need(m, n, k)
+    a1 = (m * k * 8 + 255) // 256 * 256
+    b1 = (k * n * 8 + 255) // 256 * 256
+    assert res == 4 * (2 * a1 + 2 * b1) and mn == 2 * a1 + 2 * b1
+    rq_res, rq_min = ws_need(m, n, k, 0x0F, 0x0F)
+    assert rq_res == 4 * (a1 + b1) and rq_min == a1 + b1
+    assert ws_need(m, n, k, 0x11, 0x11) == (0, 0)
+    assert ws_need(m, n, k, 0x01, 0x01) == (0, 0)
+    assert ws_need(m, n, 0) == (0, 0)
+    A, Bm, C = mat(m, k, FAKE), mat(k, n, 2 * FAKE), mat(m, n, 3 * FAKE)
+    assert check(A, Bm, C, ws=4 * FAKE, ws_bytes=mn - 1) == WORKSPACE
+    assert check(A, Bm, C, ws=None, ws_bytes=0) == WORKSPACE
+    assert check(A, Bm, C, ws=None, ws_bytes=16) == INVALID
+
+
+def test_plan_counts_match_paper():
+    """24 full, 8 real quaternion (also purely imaginary quaternion), 3
+    complex, 1 real (Sec. III A)."""
+    assert B.plan_real_gemms(0xFF, 0xFF) == 24
+    assert B.plan_real_gemms(0x0F, 0x0F) == 8
+    assert B.plan_real_gemms(0xF0, 0xF0) == 8
+    assert B.plan_real_gemms(0x11, 0x11) == 3
+    assert B.plan_real_gemms(0x01, 0x01) == 1
+    assert B.plan_real_gemms(0x00, 0xFF) == 0
+
+
+def test_degenerate_shapes_validate():
+    assert check(mat(0, 5, FAKE), mat(5, 3, 2 * FAKE), mat(0, 3, 3 * FAKE)) == OK
+    assert check(mat(4, 0, FAKE), mat(0, 3, 2 * FAKE), mat(4, 3, 3 * FAKE)) == OK
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert B.lib().bq_create(ctypes.byref(h), 0) != OK
+    assert not h.value

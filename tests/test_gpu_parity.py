@@ -1,0 +1,214 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Tolerance: relative Frobenius error over all eight blocks <= 1e-12 for
+random FP64 inputs (the accuracy target stated for the FP64 path); bit
+equality wherever every intermediate is an exactly representable integer
+(integer inputs, unit blocks).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02081_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def bq():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_02081_amd as bq
+
+    bq.lib()
+    return bq
+
+
+def dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def run(bq, A, B, **kw):
+    import torch
+
+    C = bq.bq_gemm(dev(A), dev(B), **kw)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+@pytest.mark.parametrize("m,k,n", [(256, 256, 256), (70, 50, 45), (1, 1, 1), (130, 257, 67),
+                                   (200, 16, 300), (64, 1000, 33)])
+def test_random_uniform(bq, m, k, n):
+    A, B = inputs.pair(m, k, n, "uniform", seed=1)
+    print(f"random uniform m={m} k={k} n={n}", flush=True)
+    C = run(bq, A, B)
+    assert oracle.rel_frobenius(C, oracle.gemm(A, B)) <= TOL
+
+
+@pytest.mark.parametrize("m,k,n", [(64, 64, 64), (70, 50, 45), (129, 96, 130)])
+def test_integer_bit_exact(bq, m, k, n):
+    A, B = inputs.pair(m, k, n, "int", seed=7, bound=1024)
+    print(f"integer m={m} k={k} n={n}", flush=True)
+    assert np.array_equal(run(bq, A, B), oracle.gemm(A, B))
+
+
+def test_unit_blocks_bit_exact(bq):
+    n = 48
+    for u in range(8):
+        for v in range(8):
+            A = np.zeros((8, n, n)); A[u] = np.eye(n)
+            B = np.zeros((8, n, n)); B[v] = np.eye(n)
+            assert np.array_equal(run(bq, A, B), oracle.gemm(A, B)), (u, v)
+
+
+@pytest.mark.parametrize("opA,opB", [("C", "N"), ("N", "C"), ("C", "C")])
+def test_conjugate_ops(bq, opA, opB):
+    A, B = inputs.pair(96, 80, 72, "normal", seed=3)
+    ref = oracle.gemm(oracle.conj(A) if opA == "C" else A, oracle.conj(B) if opB == "C" else B)
+    assert oracle.rel_frobenius(run(bq, A, B, opA=opA, opB=opB), ref) <= TOL
+
+
+@pytest.mark.parametrize("name", ["real_quaternion", "complex", "real"])
+def test_subalgebra_masks(bq, name):
+    mask = inputs.MASKS[name]
+    A, B = inputs.pair(100, 90, 80, "normal", seed=4, mask_a=mask, mask_b=mask)
+    C = run(bq, A, B, mask_a=mask, mask_b=mask)
+    assert oracle.rel_frobenius(C, oracle.gemm(A, B)) <= TOL
+    for c in set(range(8)) - _reach(mask):
+        assert not np.any(C[c]), c
+
+
+def _reach(mask):
+    if mask == inputs.REAL:
+        return {0}
+    if mask == inputs.COMPLEX:
+        return {0, 4}
+    if mask == inputs.REAL_QUAT:
+        return {0, 1, 2, 3}
+    return set(range(8))
+
+
+def test_variant_entry_points(bq):
+    import torch
+
+    A, B = inputs.pair(77, 65, 59, "normal", seed=5)
+    a, b = dev(A), dev(B)
+    # real
+    c = torch.empty((77, 59), dtype=torch.float64, device="cuda")
+    bq.re_gemm(a[0], b[0], c)
+    torch.cuda.synchronize()
+    assert np.allclose(c.cpu().numpy(), A[0] @ B[0], rtol=0, atol=1e-12)
+    # complex
+    cr = torch.empty_like(c); ci = torch.empty_like(c)
+    bq.cx_gemm((a[0], a[4]), (b[0], b[4]), (cr, ci))
+    torch.cuda.synchronize()
+    ref = (A[0] + 1j * A[4]) @ (B[0] + 1j * B[4])
+    assert np.allclose(cr.cpu().numpy() + 1j * ci.cpu().numpy(), ref, rtol=0, atol=1e-12)
+    # complex conjugate of A
+    bq.cx_gemm((a[0], a[4]), (b[0], b[4]), (cr, ci), opA="C")
+    torch.cuda.synchronize()
+    ref = (A[0] - 1j * A[4]) @ (B[0] + 1j * B[4])
+    assert np.allclose(cr.cpu().numpy() + 1j * ci.cpu().numpy(), ref, rtol=0, atol=1e-12)
+    # real quaternion
+    cq = [torch.empty_like(c) for _ in range(4)]
+    bq.rq_gemm([a[i] for i in range(4)], [b[i] for i in range(4)], cq)
+    torch.cuda.synchronize()
+    Aq = A.copy(); Aq[4:] = 0
+    Bq = B.copy(); Bq[4:] = 0
+    ref = oracle.gemm(Aq, Bq)
+    got = np.stack([x.cpu().numpy() for x in cq] + [np.zeros((77, 59))] * 4)
+    assert oracle.rel_frobenius(got, ref) <= TOL
+
+
+def test_streamed_equals_resident(bq):
+    A, B = inputs.pair(150, 140, 130, "uniform", seed=6)
+    C1 = run(bq, A, B)
+    C2 = run(bq, A, B, streamed=True)
+    assert np.array_equal(C1, C2)
+    assert oracle.rel_frobenius(C2, oracle.gemm(A, B)) <= TOL
+
+
+def test_guard_band_untouched(bq):
+    """C with ld > n: the padding columns keep their sentinel values."""
+    import torch
+
+    m, k, n, ld = 90, 70, 50, 64
+    A, B = inputs.pair(m, k, n, "uniform", seed=8)
+    Cbuf = torch.full((8, m, ld), 12345.0, dtype=torch.float64, device="cuda")
+    C = Cbuf[:, :, :n]
+    bq.bq_gemm(dev(A), dev(B), C)
+    torch.cuda.synchronize()
+    out = Cbuf.cpu().numpy()
+    assert np.all(out[:, :, n:] == 12345.0)
+    assert oracle.rel_frobenius(out[:, :, :n], oracle.gemm(A, B)) <= TOL
+
+
+def test_degenerate(bq):
+    import torch
+
+    A, B = inputs.pair(5, 0, 7, "uniform", seed=9)
+    C = torch.full((8, 5, 7), 3.0, dtype=torch.float64, device="cuda")
+    # k == 0: C = 0
+    bq.bq_gemm(torch.empty((8, 5, 0), dtype=torch.float64, device="cuda"),
+               torch.empty((8, 0, 7), dtype=torch.float64, device="cuda"), C)
+    torch.cuda.synchronize()
+    assert not torch.any(C).item()
+    # m == 0: no-op
+    out = bq.bq_gemm(torch.empty((8, 0, 4), dtype=torch.float64, device="cuda"),
+                     torch.zeros((8, 4, 3), dtype=torch.float64, device="cuda"))
+    assert out.shape == (8, 0, 3)
+
+
+def test_nan_row_propagation(bq):
+    A, B = inputs.pair(40, 40, 40, "uniform", seed=10)
+    A[6, 11, 3] = np.nan
+    C = run(bq, A, B)
+    assert np.all(np.isnan(C[:, 11, :]))
+    assert not np.any(np.isnan(np.delete(C, 11, axis=1)))
+
+
+def test_error_leaves_c_untouched(bq):
+    import torch
+
+    A, B = inputs.pair(32, 32, 32, "uniform", seed=11)
+    C = torch.full((8, 32, 32), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(bq.BqError) as e:
+        bq.bq_gemm(dev(A), dev(B), C, opA="T")
+    assert e.value.code == 2
+    torch.cuda.synchronize()
+    assert torch.all(C == 7.0).item()
+
+
+def _sample(n, r, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n - 1, size=r - 1, replace=False))
+    return np.append(idx, n - 1)
+
+
+@pytest.mark.parametrize("name", ["biquaternion", "real_quaternion", "complex", "real"])
+def test_n4096_sampled(bq, name):
+    """n = 4096, N(0,1) entries, each subalgebra; rows/cols sampled (the last
+    row and column always included) and checked against the oracle."""
+    import torch
+
+    n, r = 4096, 96
+    mask = inputs.MASKS[name]
+    print(f"n=4096 {name}: drawing inputs", flush=True)
+    A, B = inputs.pair(n, n, n, "normal", seed=2, mask_a=mask, mask_b=mask)
+    C = bq.bq_gemm(dev(A), dev(B), mask_a=mask, mask_b=mask)
+    torch.cuda.synchronize()
+    rows, cols = _sample(n, r, 21), _sample(n, r, 22)
+    Cs = C[:, torch.as_tensor(rows, device="cuda")][:, :, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    ref = oracle.gemm(A[:, rows, :], B[:, :, cols])
+    err = oracle.rel_frobenius(Cs, ref)
+    print(f"n=4096 {name}: rel err {err:.3e}", flush=True)
+    assert err <= TOL
+    # the isomorph: Z(C) = Z(A) Z(B) on the sampled block
+    ZA = oracle.iso(A[:, rows, :])
+    ZB = oracle.iso(B[:, :, cols])
+    assert oracle.rel_frobenius(Cs, oracle.iso_inv(ZA @ ZB)) <= TOL
