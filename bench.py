@@ -1,0 +1,179 @@
+"""Benchmark of the bilinear biquaternion GEMM on one MI355X.
+
+One step = one complete product C = A.B through the C-ABI (bq_gemm): the
+Hadamard pre-combinations, the eight Gauss-fused complex-product GEMM launches
+(24 real FP64 GEMMs) with the post-combination in their epilogues.  Inputs are
+resident in HBM before the timed region starts.
+
+Workload (default): n = 16384, A Fock-like and B density-like Hermitian
+biquaternions U diag(lambda) U^H with lambda over 1e0..1e-8 (seeded,
+synthetic).  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6           # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
+METRIC = "BQ-GEMM effective TFLOP/s & MFMA % at n=16384; FP64 vs split-prec @1e-12 rel"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_gauss_n16384.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_02081_amd", "csrc", "bq_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_per_launch():
+    """HBM bytes per launch from committed rocprofv3 counters, if they were
+    taken on the kernel source as it is now."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def sample_idx(n, r, seed):
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n - 1, size=r - 1, replace=False))
+    return np.append(idx, n - 1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=384,
+                    help="rows/cols of the sub-block the oracle recomputes (0: skip)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only; run it with --gpus 1 "
+              "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2609_02081_amd as bq
+    from paper_2609_02081_amd import inputs
+
+    n = args.n
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bq.lib()
+    log(f"building Hermitian inputs n={n} on the device")
+    t0 = time.time()
+    A, B = inputs.hermitian_pair(n, args.seed, dev)
+    C = torch.empty_like(A)
+    res, _ = bq.workspace_size(n, n, n)
+    ws = torch.empty(res, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f}s; workspace {res / 2**30:.1f} GiB")
+
+    for i in range(args.warmup):
+        bq.bq_gemm(A, B, C, workspace=ws)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+
+    bq.trace_enable(True)
+    bq.trace_read()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(args.steps):
+        bq.bq_gemm(A, B, C, workspace=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    recs = bq.trace_read()
+    bq.trace_enable(False)
+    log(f"timed {args.steps} steps: {total_ms:.1f} ms")
+
+    ms = total_ms / args.steps
+    real_gemms = bq.plan_real_gemms(bq.FULL, bq.FULL)
+    flop_eff = 64 * 2.0 * n ** 3
+    flop_exec = real_gemms * 2.0 * n ** 3
+    eff_tflops = flop_eff / (ms * 1e-3) / 1e12
+    exec_tflops = flop_exec / (ms * 1e-3) / 1e12
+
+    gemm = [r for r in recs if r["kernel"] == "gemm_gauss"]
+    comb = [r for r in recs if r["kernel"] == "combine"]
+    g_ms = sum(r["ms"] for r in gemm) / max(1, len(gemm))
+    g_flops = gemm[0]["flops"] if gemm else 0.0
+    achieved = g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0
+    c_ms = sum(r["ms"] for r in comb) / max(1, len(comb))
+    c_bytes = comb[0]["bytes"] if comb else 0.0
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": traffic_per_launch(),
+                "kernel": "cgemm_f64<GAUSS> (one complex product, 3 real FP64 GEMMs)",
+                "launches": len(gemm), "avg_launch_ms": round(g_ms, 3),
+                "flops_per_launch": g_flops}
+    combine = {"bound": "hbm", "avg_launch_ms": round(c_ms, 4), "bytes_per_launch": c_bytes,
+               "achieved_GBs": round(c_bytes / (c_ms * 1e-3) / 1e9, 1) if c_ms > 0 else None,
+               "peak_GBs": PEAK_HBM_GBS, "launches": len(comb)}
+
+    cpu = None
+    rel_err = None
+    if args.cpu_sample > 0:
+        import oracle
+
+        r = args.cpu_sample
+        rows, cols = sample_idx(n, r, 101), sample_idx(n, r, 102)
+        ri = torch.as_tensor(rows, device=dev)
+        ci = torch.as_tensor(cols, device=dev)
+        As = A[:, ri, :].cpu().numpy()
+        Bs = B[:, :, ci].cpu().numpy()
+        Cs = C[:, ri][:, :, ci].cpu().numpy()
+        log(f"oracle on a {r}x{r} sampled sub-block (k = {n}) with {oracle.num_threads()} threads")
+        t0 = time.perf_counter()
+        ref = oracle.gemm(As, Bs)
+        t_cpu = time.perf_counter() - t0
+        rel_err = oracle.rel_frobenius(Cs, ref)
+        cpu = {"value": round(64 * 2.0 * r * r * n / t_cpu / 1e12, 6),
+               "unit": "effective TFLOP/s (64 real GEMMs counted)", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"C[R,S] for {r} sampled rows R and {r} columns S (last row/column included) "
+                         f"of the n={n} product, full k={n}: {t_cpu:.2f} s",
+               "seconds": round(t_cpu, 3)}
+        log(f"oracle {t_cpu:.1f}s, sampled rel Frobenius error {rel_err:.3e}")
+
+    out = {"metric": METRIC, "value": round(eff_tflops, 3), "unit": "effective TFLOP/s (64 real GEMMs counted)",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"biquaternion GEMM C=A.B, n={n}, A Fock-like x B density-like "
+                                  "Hermitian (U diag(lambda) U^H, lambda 1e0..1e-8), FP64 bilinear 24-GEMM",
+                      "n": n, "prec": "fp64", "real_gemms": real_gemms, "seed": args.seed},
+           "executed_tflops": round(exec_tflops, 3),
+           "mfma_frac_of_fp64_peak": round(exec_tflops / PEAK_FP64_TFLOPS, 4),
+           "rel_err_sampled_vs_oracle": rel_err,
+           "roofline": roofline, "combine": combine, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

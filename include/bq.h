@@ -137,6 +137,34 @@ bq_status_t bq_rq_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B
  * 24 full, 8 real quaternion, 3 complex, 1 real).  Host only. */
 int bq_plan_real_gemms(unsigned maskA, unsigned maskB);
 
+/* Launch tracing (measurement support, not part of the product semantics).
+ * While enabled, every kernel the handle enqueues is bracketed by a pair of
+ * HIP events recorded on the same stream.  bq_trace_read waits for the
+ * recorded events, copies up to `cap` records (oldest first), removes them
+ * and sets *count to the number copied.  `flops` and `bytes` are the
+ * algorithmic work of the launch: 2 m n k per real product for a GEMM,
+ * the bytes read plus written for a pre-combination or zero fill. */
+typedef enum {
+  BQ_KERNEL_GEMM_GAUSS = 0, /* complex x complex, 3 real products    */
+  BQ_KERNEL_GEMM_RC = 1,    /* real x complex, 2 real products       */
+  BQ_KERNEL_GEMM_CR = 2,    /* complex x real, 2 real products       */
+  BQ_KERNEL_GEMM_RR = 3,    /* real x real, 1 real product           */
+  BQ_KERNEL_COMBINE = 10,   /* Hadamard pre-combination              */
+  BQ_KERNEL_FILL = 11       /* zero fill of a structurally zero block */
+} bq_kernel_t;
+
+typedef struct {
+  int kernel; /* bq_kernel_t */
+  int config; /* tile configuration of a GEMM launch, else -1 */
+  int64_t m, n, k;
+  double ms;
+  double flops;
+  double bytes;
+} bq_trace_record_t;
+
+bq_status_t bq_trace_enable(bq_handle_t h, int enable);
+bq_status_t bq_trace_read(bq_handle_t h, bq_trace_record_t* recs, int cap, int* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,15 @@ class BqMatrix(ctypes.Structure):
                 ("cols", ctypes.c_int64), ("ld", ctypes.c_int64)]
 
 
+class BqTraceRecord(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("config", ctypes.c_int), ("m", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+KERNEL_NAMES = {0: "gemm_gauss", 1: "gemm_rc", 2: "gemm_cr", 3: "gemm_rr", 10: "combine", 11: "fill"}
+
+
 class BqError(RuntimeError):
     def __init__(self, code: int, detail: str):
         super().__init__(f"{STATUS.get(code, code)}: {detail}")
@@ -54,6 +63,9 @@ _SIGS = [
     ("bq_rq_gemm", ctypes.c_int,
      [ctypes.c_void_p, _M, _M, _M, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("bq_plan_real_gemms", ctypes.c_int, [ctypes.c_uint, ctypes.c_uint]),
+    ("bq_trace_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("bq_trace_read", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(BqTraceRecord), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 ]
 
 
@@ -205,3 +217,21 @@ def rq_gemm(A, B, C, workspace=None, stream=None):
                            ctypes.byref(Cm), ctypes.c_void_p(workspace.data_ptr()),
                            workspace.numel(), _stream(stream)))
     return C
+
+
+def trace_enable(enable: bool = True, device: int = 0) -> None:
+    check(lib().bq_trace_enable(handle(device), int(bool(enable))))
+
+
+def trace_read(device: int = 0, cap: int = 4096) -> list[dict]:
+    """Completed launch records since the last read (waits for them)."""
+    recs = (BqTraceRecord * cap)()
+    cnt = ctypes.c_int()
+    out = []
+    while True:
+        check(lib().bq_trace_read(handle(device), recs, cap, ctypes.byref(cnt)))
+        for r in recs[:cnt.value]:
+            out.append({"kernel": KERNEL_NAMES.get(r.kernel, str(r.kernel)), "config": r.config,
+                        "m": r.m, "n": r.n, "k": r.k, "ms": r.ms, "flops": r.flops, "bytes": r.bytes})
+        if cnt.value < cap:
+            return out

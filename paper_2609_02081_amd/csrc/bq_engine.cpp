@@ -12,10 +12,17 @@
 #include "bq.h"
 #include "bq_internal.h"
 
+struct TraceSlot {
+  hipEvent_t start, stop;
+  bq_trace_record_t rec;
+};
+
 struct bq_handle_s {
   int device;
   int cu_count;
   std::string arch;
+  bool trace = false;
+  std::vector<TraceSlot> pending;
 };
 
 namespace {
@@ -305,8 +312,38 @@ bq_status_t hip_fail(hipError_t e, const char* what) {
   return fail(BQ_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Brackets one launch with events when the handle traces.
+struct Tracer {
+  bq_handle_t h;
+  hipStream_t s;
+  TraceSlot slot{};
+  bool on = false;
+  Tracer(bq_handle_t hh, hipStream_t ss, int kernel, int cfg, int64_t m, int64_t n, int64_t k, double flops,
+         double bytes)
+      : h(hh), s(ss) {
+    if (!h || !h->trace) return;
+    if (hipEventCreate(&slot.start) != hipSuccess) return;
+    if (hipEventCreate(&slot.stop) != hipSuccess) {
+      (void)hipEventDestroy(slot.start);
+      return;
+    }
+    slot.rec = {kernel, cfg, m, n, k, 0.0, flops, bytes};
+    on = hipEventRecord(slot.start, s) == hipSuccess;
+  }
+  void done() {
+    if (!on) return;
+    if (hipEventRecord(slot.stop, s) == hipSuccess) {
+      h->pending.push_back(slot);
+    } else {
+      (void)hipEventDestroy(slot.start);
+      (void)hipEventDestroy(slot.stop);
+    }
+    on = false;
+  }
+};
+
 // Enqueue the plan.  Validation has passed.
-bq_status_t execute(const Plan& pl, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C,
+bq_status_t execute(bq_handle_t h, const Plan& pl, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C,
                     unsigned out_mask, void* ws, bool streamed, hipStream_t s) {
   const int64_t m = A->rows, n = B->cols, k = A->cols;
   if (m == 0 || n == 0) return BQ_OK;
@@ -338,12 +375,19 @@ bq_status_t execute(const Plan& pl, const bq_matrix_t* A, const bq_matrix_t* B, 
     ca.cols = left ? k : n;
     ca.ldd = ca.cols;
     ca.nq = nq;
+    int nsrc = 0, ndst = 0;
+    for (int c = 0; c < 8; ++c) nsrc += (ca.src[c] != nullptr);
     for (int j = 0; j < nq; ++j) {
       ca.dst_r[j] = left ? cA_r[slot0 + j] : cB_r[slot0 + j];
       ca.dst_i[j] = left ? cA_i[slot0 + j] : cB_i[slot0 + j];
+      ndst += (ca.dst_r[j] != nullptr) + (ca.dst_i[j] != nullptr);
       for (int u = 0; u < 4; ++u) ca.w[j][u] = left ? pl.wA[q0 + j][u] : pl.wB[q0 + j][u];
     }
-    return bq::launch_combine(ca, s);
+    Tracer tr(h, s, BQ_KERNEL_COMBINE, -1, ca.rows, ca.cols, 0, 0.0,
+              double(nsrc + ndst) * double(ca.rows) * double(ca.cols) * 8.0);
+    hipError_t e = bq::launch_combine(ca, s);
+    tr.done();
+    return e;
   };
 
   if (k > 0 && pl.bilinear && !streamed) {
@@ -408,12 +452,17 @@ bq_status_t execute(const Plan& pl, const bq_matrix_t* A, const bq_matrix_t* B, 
     }
     if (g.ntgt == 0) continue;
     const int cfg = cfg_override >= 0 ? cfg_override : bq::default_tile_config(kind, m, n, k);
+    const int nprod = kind == bq::KIND_GAUSS ? 3 : (kind == bq::KIND_RR ? 1 : 2);
+    Tracer tr(h, s, kind, cfg, m, n, k, double(nprod) * 2.0 * double(m) * double(n) * double(k), 0.0);
     hipError_t e = bq::launch_cgemm(kind, g, cfg, s);
+    tr.done();
     if (e != hipSuccess) return hip_fail(e, "GEMM launch");
   }
   for (int c = 0; c < 8; ++c) {
     if ((out_mask >> c & 1) && !touched[c]) {
+      Tracer tr(h, s, BQ_KERNEL_FILL, -1, m, n, 0, 0.0, double(m) * double(n) * 8.0);
       hipError_t e = bq::launch_fill_zero(C->comp[c], m, n, C->ld, s);
+      tr.done();
       if (e != hipSuccess) return hip_fail(e, "zero-fill launch");
     }
   }
@@ -442,7 +491,7 @@ bq_status_t run(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, c
   if (st != BQ_OK) return st;
   st = check_handle(h);
   if (st != BQ_OK) return st;
-  return execute(plan, A, B, C, out_mask, ws, streamed, static_cast<hipStream_t>(stream));
+  return execute(h, plan, A, B, C, out_mask, ws, streamed, static_cast<hipStream_t>(stream));
 }
 
 bq_matrix_t restrict_to(const bq_matrix_t* X, unsigned mask) {
@@ -477,7 +526,38 @@ bq_status_t bq_create(bq_handle_t* h, int device) {
 }
 
 bq_status_t bq_destroy(bq_handle_t h) {
+  if (h) {
+    for (TraceSlot& t : h->pending) {
+      (void)hipEventDestroy(t.start);
+      (void)hipEventDestroy(t.stop);
+    }
+  }
   delete h;
+  return BQ_OK;
+}
+
+bq_status_t bq_trace_enable(bq_handle_t h, int enable) {
+  if (!h) return fail(BQ_ERR_INVALID_VALUE, "handle is null");
+  h->trace = enable != 0;
+  return BQ_OK;
+}
+
+bq_status_t bq_trace_read(bq_handle_t h, bq_trace_record_t* recs, int cap, int* count) {
+  if (!h || !count || cap < 0 || (cap > 0 && !recs)) return fail(BQ_ERR_INVALID_VALUE, "bad trace_read argument");
+  const int ncopy = std::min<int>(cap, (int)h->pending.size());
+  for (int i = 0; i < ncopy; ++i) {
+    TraceSlot& t = h->pending[i];
+    hipError_t e = hipEventSynchronize(t.stop);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+    if (e != hipSuccess) return hip_fail(e, "trace event");
+    recs[i] = t.rec;
+    recs[i].ms = ms;
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  h->pending.erase(h->pending.begin(), h->pending.begin() + ncopy);
+  *count = ncopy;
   return BQ_OK;
 }
 

@@ -141,3 +141,11 @@ def device_uniform(n_rows: int, n_cols: int, seed: int, device, count: int = 8):
     t = torch.empty((count, n_rows, n_cols), dtype=torch.float64, device=device)
     t.uniform_(-1.0, 1.0, generator=g)
     return t
+
+
+def hermitian_pair(n: int, seed: int, device="cpu"):
+    """A Fock-like (signed spectrum, `seed`) and B density-like (positive
+    spectrum, `seed + 1`) Hermitian biquaternions, each (8, n, n)."""
+    A = hermitian_blocks(hermitian_params(n, seed, "fock"), device)
+    B = hermitian_blocks(hermitian_params(n, seed + 1, "density"), device)
+    return A, B
