@@ -250,6 +250,11 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
       if (M[t]->comp[c] && misaligned(M[t]->comp[c]))
         return fail(BQ_ERR_INVALID_VALUE, std::string(nm[t]) + ": component not 8-byte aligned");
   }
+  // Kernels keep offsets inside a tile in 32 bits: 128 rows of any leading
+  // dimension must span fewer than 2^32 elements.
+  for (int t = 0; t < 3; ++t)
+    if (M[t]->ld > (int64_t(1) << 24))
+      return fail(BQ_ERR_UNSUPPORTED, std::string(nm[t]) + ": ld above 2^24 elements is not supported");
   if (A->cols != B->rows) return fail(BQ_ERR_INVALID_VALUE, "A.cols != B.rows");
   if (C->rows != A->rows || C->cols != B->cols)
     return fail(BQ_ERR_INVALID_VALUE, "C must be A.rows x B.cols");
@@ -432,6 +437,8 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const bq_matrix_t* A, const b
     g.sL = L.s; g.sR = R.s;
     g.ldc = C->ld;
     g.ntgt = 0;
+    auto al16 = [](const double* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    g.vec = (g.lda % 2 == 0) && (g.ldb % 2 == 0) && al16(g.lr) && al16(g.li) && al16(g.rr) && al16(g.ri);
     for (const Tgt& t : p.tgts) {
       const Cplx c = cmul(t.coef, rot);
       const bool out_r = (c.re != 0.0 && pr_nz) || (c.im != 0.0 && pi_nz);

@@ -41,7 +41,7 @@ struct GemmArgs {
   int64_t m, n, k;
   double sL, sR;
   int ntgt;
-  int pad_;
+  int vec;  // 1: lda, ldb even and operand bases 16-byte aligned
   Target tgt[kMaxTargets];
   int64_t ldc;
 };

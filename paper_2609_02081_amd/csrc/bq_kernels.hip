@@ -72,13 +72,16 @@ cgemm_f64(const GemmArgs g) {
   constexpr int NB = HAS_RI ? 2 : 1;
   constexpr int NACC = KIND == KIND_GAUSS ? 3 : (KIND == KIND_RR ? 1 : 2);
   constexpr int PAD = 4;
-  constexpr int A_PER = BM * BK / NT;
-  constexpr int B_PER = BK * BN / NT;
-  static_assert(A_PER * NT == BM * BK && B_PER * NT == BK * BN, "tile / thread mismatch");
+  // Elements are moved in pairs along the contiguous dimension.
+  constexpr int A_PAIRS = BM * BK / 2 / NT;
+  constexpr int B_PAIRS = BK * BN / 2 / NT;
+  static_assert(A_PAIRS * NT * 2 == BM * BK && B_PAIRS * NT * 2 == BK * BN, "tile / thread mismatch");
   static_assert(BK % 4 == 0 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
+  static_assert(((BN + PAD) * 8) % 16 == 0, "B rows must stay 16-byte aligned in LDS");
 
-  __shared__ double As[NA][BK][BM + PAD];
-  __shared__ double Bs[NB][BK][BN + PAD];
+  // Double-buffered LDS: the A tile k-major (As[k][i]), the B tile as stored.
+  __shared__ double As[2][NA][BK][BM + PAD];
+  __shared__ __attribute__((aligned(16))) double Bs[2][NB][BK][BN + PAD];
 
   const int tiles_m = (int)((g.m + BM - 1) / BM);
   const int tiles_n = (int)((g.n + BN - 1) / BN);
@@ -95,72 +98,92 @@ cgemm_f64(const GemmArgs g) {
   const int fr = lane & 15;
   const int fk = lane >> 4;
 
-  // Per-tile base pointers: all further offsets stay small.
+  // Per-tile base pointers: all further offsets stay small (32-bit).
   const double* pa[2] = {g.lr + m0 * g.lda, HAS_LI ? g.li + m0 * g.lda : nullptr};
   const double* pb[2] = {g.rr + n0, HAS_RI ? g.ri + n0 : nullptr};
   const int64_t mrem = g.m - m0;
   const int64_t nrem = g.n - n0;
+  // Interior tiles with 16-byte aligned rows load without bounds checks.
+  const bool fast = g.vec && mrem >= BM && nrem >= BN;
 
-  double ra[NA][A_PER];
-  double rb[NB][B_PER];
-
-  // Per-thread element offsets inside a K-tile: fixed for the whole loop,
-  // 32-bit (the host guarantees BM * lda and BK * ldb fit).
-  uint32_t offA[A_PER], offB[B_PER];
-  uint32_t okA = 0, okB = 0;  // row / column inside the matrix, per element
-#pragma unroll
-  for (int i = 0; i < A_PER; ++i) {
-    const int e = tid + i * NT;
-    const int r = e / BK, c = e % BK;
-    offA[i] = (uint32_t)r * (uint32_t)g.lda + (uint32_t)c;
-    okA |= (uint32_t)(r < mrem) << i;
-  }
-#pragma unroll
-  for (int i = 0; i < B_PER; ++i) {
-    const int e = tid + i * NT;
-    const int r = e / BN, c = e % BN;
-    offB[i] = (uint32_t)r * (uint32_t)g.ldb + (uint32_t)c;
-    okB |= (uint32_t)(c < nrem) << i;
-  }
+  double ra[NA][2 * A_PAIRS];
+  double rb[NB][2 * B_PAIRS];
 
   auto gload = [&](int64_t k0) {
     const bool kfull = (k0 + BK <= g.k);
-    const int64_t kleft = g.k - k0;
+    if (fast && kfull) {
 #pragma unroll
-    for (int p = 0; p < NA; ++p) {
-      const double* base = pa[p] + k0;
+      for (int p = 0; p < NA; ++p) {
+        const double* base = pa[p] + k0;
 #pragma unroll
-      for (int i = 0; i < A_PER; ++i) {
-        const int c = (tid + i * NT) % BK;
-        const bool ok = ((okA >> i) & 1) && (kfull || c < kleft);
-        ra[p][i] = ok ? base[offA[i]] : 0.0;
+        for (int i = 0; i < A_PAIRS; ++i) {
+          const int v = tid + i * NT;
+          const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
+          const d2 x = *reinterpret_cast<const d2*>(base + (uint32_t)(r * (uint32_t)g.lda + c));
+          ra[p][2 * i] = x[0];
+          ra[p][2 * i + 1] = x[1];
+        }
       }
-    }
 #pragma unroll
-    for (int p = 0; p < NB; ++p) {
-      const double* base = pb[p] + k0 * g.ldb;
+      for (int p = 0; p < NB; ++p) {
+        const double* base = pb[p] + k0 * g.ldb;
 #pragma unroll
-      for (int i = 0; i < B_PER; ++i) {
-        const int r = (tid + i * NT) / BN;
-        const bool ok = ((okB >> i) & 1) && (kfull || r < kleft);
-        rb[p][i] = ok ? base[offB[i]] : 0.0;
+        for (int i = 0; i < B_PAIRS; ++i) {
+          const int v = tid + i * NT;
+          const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
+          const d2 x = *reinterpret_cast<const d2*>(base + (uint32_t)(r * (uint32_t)g.ldb + c));
+          rb[p][2 * i] = x[0];
+          rb[p][2 * i + 1] = x[1];
+        }
+      }
+    } else {
+      const int64_t kleft = g.k - k0;
+#pragma unroll
+      for (int p = 0; p < NA; ++p) {
+        const double* base = pa[p] + k0;
+#pragma unroll
+        for (int i = 0; i < A_PAIRS; ++i) {
+          const int v = tid + i * NT;
+          const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
+          const bool rok = r < mrem;
+          const uint32_t off = (uint32_t)(r * (uint32_t)g.lda + c);
+          ra[p][2 * i] = (rok && c < kleft) ? base[off] : 0.0;
+          ra[p][2 * i + 1] = (rok && c + 1 < kleft) ? base[off + 1] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NB; ++p) {
+        const double* base = pb[p] + k0 * g.ldb;
+#pragma unroll
+        for (int i = 0; i < B_PAIRS; ++i) {
+          const int v = tid + i * NT;
+          const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
+          const bool kok = r < kleft;
+          const uint32_t off = (uint32_t)(r * (uint32_t)g.ldb + c);
+          rb[p][2 * i] = (kok && c < nrem) ? base[off] : 0.0;
+          rb[p][2 * i + 1] = (kok && c + 1 < nrem) ? base[off + 1] : 0.0;
+        }
       }
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
-      const int e = tid + i * NT;
-      const int r = e / BK, c = e % BK;
+    for (int i = 0; i < A_PAIRS; ++i) {
+      const int v = tid + i * NT;
+      const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
 #pragma unroll
-      for (int p = 0; p < NA; ++p) As[p][c][r] = ra[p][i];
+      for (int p = 0; p < NA; ++p) {
+        As[buf][p][c][r] = ra[p][2 * i];
+        As[buf][p][c + 1][r] = ra[p][2 * i + 1];
+      }
     }
 #pragma unroll
-    for (int i = 0; i < B_PER; ++i) {
-      const int e = tid + i * NT;
-      const int r = e / BN, c = e % BN;
+    for (int i = 0; i < B_PAIRS; ++i) {
+      const int v = tid + i * NT;
+      const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
 #pragma unroll
-      for (int p = 0; p < NB; ++p) Bs[p][r][c] = rb[p][i];
+      for (int p = 0; p < NB; ++p)
+        *reinterpret_cast<d2*>(&Bs[buf][p][r][c]) = d2{rb[p][2 * i], rb[p][2 * i + 1]};
     }
   };
 
@@ -174,10 +197,13 @@ cgemm_f64(const GemmArgs g) {
 
   const double sL = g.sL, sR = g.sR;
   const int64_t nk = (g.k + BK - 1) / BK;
-  if (nk > 0) gload(0);
+  if (nk > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
-    lstore();
-    __syncthreads();
+    const int buf = (int)(kt & 1);
     if (kt + 1 < nk) gload((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
@@ -186,23 +212,23 @@ cgemm_f64(const GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int p = 0; p < NA; ++p) a[p][i] = As[p][krow][wm0 + i * 16 + fr];
+        for (int p = 0; p < NA; ++p) a[p][i] = As[buf][p][krow][wm0 + i * 16 + fr];
 #pragma unroll
       for (int j = 0; j < NI; ++j)
 #pragma unroll
-        for (int p = 0; p < NB; ++p) b[p][j] = Bs[p][krow][wn0 + j * 16 + fr];
+        for (int p = 0; p < NB; ++p) b[p][j] = Bs[buf][p][krow][wn0 + j * 16 + fr];
       if constexpr (KIND == KIND_GAUSS) {
         double as[MI], bs[NI];
 #pragma unroll
-        for (int i = 0; i < MI; ++i) as[i] = __builtin_fma(sL, a[HAS_LI ? 1 : 0][i], a[0][i]);
+        for (int i = 0; i < MI; ++i) as[i] = __builtin_fma(sL, a[NA - 1][i], a[0][i]);
 #pragma unroll
-        for (int j = 0; j < NI; ++j) bs[j] = __builtin_fma(sR, b[HAS_RI ? 1 : 0][j], b[0][j]);
+        for (int j = 0; j < NI; ++j) bs[j] = __builtin_fma(sR, b[NB - 1][j], b[0][j]);
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NI; ++j) {
             acc[0][i][j] = mfma_f64(a[0][i], b[0][j], acc[0][i][j]);
-            acc[1][i][j] = mfma_f64(a[HAS_LI ? 1 : 0][i], b[HAS_RI ? 1 : 0][j], acc[1 % NACC][i][j]);
+            acc[1 % NACC][i][j] = mfma_f64(a[NA - 1][i], b[NB - 1][j], acc[1 % NACC][i][j]);
             acc[2 % NACC][i][j] = mfma_f64(as[i], bs[j], acc[2 % NACC][i][j]);
           }
       } else {
@@ -218,6 +244,7 @@ cgemm_f64(const GemmArgs g) {
           }
       }
     }
+    if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
   }
 
@@ -236,7 +263,7 @@ cgemm_f64(const GemmArgs g) {
         double pr, pi;
         if constexpr (KIND == KIND_GAUSS) {
           const double t1 = acc[0][i][j][v];
-          const double t2 = acc[1][i][j][v];
+          const double t2 = acc[1 % NACC][i][j][v];
           const double t3 = acc[2 % NACC][i][j][v];
           pr = t1 - sig * t2;
           pi = (t3 - t1) - sig * t2;

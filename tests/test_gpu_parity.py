@@ -212,3 +212,29 @@ def test_n4096_sampled(bq, name):
     ZA = oracle.iso(A[:, rows, :])
     ZB = oracle.iso(B[:, :, cols])
     assert oracle.rel_frobenius(Cs, oracle.iso_inv(ZA @ ZB)) <= TOL
+
+
+@pytest.mark.parametrize("n,streamed", [(16384, False), (24576, True)])
+def test_large_hermitian_sampled(bq, n, streamed):
+    """n = 16384 and 24576 (the 2n x 2n complex isomorph has more than 2^31
+    elements at 24576, and one block is 4.8 GB > 2^32 bytes): Fock-like A
+    times density-like B, checked on sampled rows and columns that always
+    include the last ones (largest offsets)."""
+    import torch
+
+    print(f"n={n}: building Hermitian inputs on the device", flush=True)
+    A, B = inputs.hermitian_pair(n, 3, "cuda")
+    C = bq.bq_gemm(A, B, streamed=streamed)
+    torch.cuda.synchronize()
+    print(f"n={n}: product done", flush=True)
+    r = 64
+    rows, cols = _sample(n, r, 31), _sample(n, r, 32)
+    ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+    As = A[:, ri, :].cpu().numpy()
+    Bs = B[:, :, ci].cpu().numpy()
+    Cs = C[:, ri][:, :, ci].cpu().numpy()
+    del A, B, C
+    torch.cuda.empty_cache()
+    err = oracle.rel_frobenius(Cs, oracle.gemm(As, Bs))
+    print(f"n={n}: sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL
