@@ -48,6 +48,58 @@ def traffic_per_launch():
     return t.get("bytes_per_launch")
 
 
+def copy_calibration(nbytes):
+    """A plain copy of known size: the counters must read nbytes fetched and
+    nbytes written per dispatch; the ratio calibrates FETCH_SIZE/WRITE_SIZE."""
+    import torch
+
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copied {nbytes} bytes 3 times")
+
+
+def _pmc_rows(d, counter):
+    """(kernel name, value) per dispatch from a rocprofv3 csv output tree."""
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, copy_bytes):
+    def mean_for(rows, pred):
+        v = [x for name, x in rows if pred(name)]
+        return sum(v) / len(v) if v else None
+    is_gemm = lambda name: "cgemm_f64<0," in name
+    is_copy = lambda name: "copy" in name.lower() or "elementwise" in name.lower()
+    f_kib = mean_for(_pmc_rows(fetch_dir, "FETCH_SIZE"), is_gemm)
+    w_kib = mean_for(_pmc_rows(write_dir, "WRITE_SIZE"), is_gemm)
+    cf = max((x for name, x in _pmc_rows(cal_fetch_dir, "FETCH_SIZE") if is_copy(name)), default=None)
+    cw = max((x for name, x in _pmc_rows(cal_write_dir, "WRITE_SIZE") if is_copy(name)), default=None)
+    if None in (f_kib, w_kib, cf, cw):
+        raise SystemExit(f"missing counters: {f_kib} {w_kib} {cf} {cw}")
+    kf = copy_bytes / (cf * 1024.0)
+    kw = copy_bytes / (cw * 1024.0)
+    out = {"kernel": "cgemm_f64<GAUSS> (tile config 0)", "workload": "n=16384 biquaternion product",
+           "kernel_source_sha256": kernel_sha(),
+           "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
+           "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": kf, "write_scale": kw,
+           "bytes_per_launch": f_kib * 1024.0 * kf + w_kib * 1024.0 * kw}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def sample_idx(n, r, seed):
     import numpy as np
 
@@ -63,9 +115,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=384,
+    ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="rows/cols of the sub-block the oracle recomputes (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (calibrates the HBM counters)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="turn four rocprofv3 --pmc runs (csv) into the committed traffic summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, copy_bytes=args.copy_calibration or (1 << 32))
+        return
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build measures one GPU only; run it with --gpus 1 "

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -306,6 +307,19 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
   return BQ_OK;
 }
 
+// Tile order (BQ_TILE_ORDER="xcd,group_m" overrides the default "1,8").
+void tile_order(int* xcd, int* group) {
+  *xcd = 1;
+  *group = 8;
+  const char* e = std::getenv("BQ_TILE_ORDER");
+  if (!e || !*e) return;
+  int a = 1, b = 8;
+  if (std::sscanf(e, "%d,%d", &a, &b) == 2 && b >= 1) {
+    *xcd = a != 0;
+    *group = b;
+  }
+}
+
 int tile_override() {
   const char* e = std::getenv("BQ_TILE_CONFIG");
   if (!e || !*e) return -1;
@@ -437,6 +451,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const bq_matrix_t* A, const b
     g.sL = L.s; g.sR = R.s;
     g.ldc = C->ld;
     g.ntgt = 0;
+    tile_order(&g.xcd_remap, &g.group_m);
     auto al16 = [](const double* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
     g.vec = (g.lda % 2 == 0) && (g.ldb % 2 == 0) && al16(g.lr) && al16(g.li) && al16(g.rr) && al16(g.ri);
     for (const Tgt& t : p.tgts) {

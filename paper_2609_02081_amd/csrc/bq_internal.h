@@ -44,6 +44,8 @@ struct GemmArgs {
   int vec;  // 1: lda, ldb even and operand bases 16-byte aligned
   Target tgt[kMaxTargets];
   int64_t ldc;
+  int xcd_remap;  // 1: deal contiguous tile ranges to the 8 XCDs
+  int group_m;    // tile-rows per group of the grouped tile order (>= 1)
 };
 
 // Linear combinations of quaternion components (the Hadamard rows of

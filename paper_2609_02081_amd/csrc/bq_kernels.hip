@@ -27,18 +27,21 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 // groups of GROUP_M tile-rows so tiles that run together share A and B panels
 // in their XCD's L2.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
+__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int xcd_remap, int group_m, int& tm,
+                                            int& tn) {
   constexpr int kXcd = 8;
-  constexpr int kGroupM = 8;
   const int T = tiles_m * tiles_n;
   const int w = blockIdx.x;
-  const int x = w % kXcd, slot = w / kXcd;
-  const int base = T / kXcd, rem = T % kXcd;
-  const int t = x * base + (x < rem ? x : rem) + slot;
-  const int per_group = kGroupM * tiles_n;
+  int t = w;
+  if (xcd_remap) {
+    const int x = w % kXcd, slot = w / kXcd;
+    const int base = T / kXcd, rem = T % kXcd;
+    t = x * base + (x < rem ? x : rem) + slot;
+  }
+  const int per_group = group_m * tiles_n;
   const int group = t / per_group;
-  const int first_m = group * kGroupM;
-  const int gm = min(tiles_m - first_m, kGroupM);
+  const int first_m = group * group_m;
+  const int gm = min(tiles_m - first_m, group_m);
   const int in_g = t - group * per_group;
   tm = first_m + in_g % gm;
   tn = in_g / gm;
@@ -86,7 +89,7 @@ cgemm_f64(const GemmArgs g) {
   const int tiles_m = (int)((g.m + BM - 1) / BM);
   const int tiles_n = (int)((g.n + BN - 1) / BN);
   int tm, tn;
-  tile_coords(tiles_m, tiles_n, tm, tn);
+  tile_coords(tiles_m, tiles_n, g.xcd_remap, g.group_m, tm, tn);
   const int64_t m0 = (int64_t)tm * BM;
   const int64_t n0 = (int64_t)tn * BN;
 
