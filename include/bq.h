@@ -53,14 +53,21 @@ typedef enum {
  * This build implements N and C; T and H return BQ_ERR_UNSUPPORTED. */
 typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
 
-/* Arithmetic of the real GEMMs.  FP64: FP64 MFMA.  The split forms slice
- * each FP64 operand into `slices` low-precision pieces with power-of-two
- * scaling per row (left operand) / column (right operand), multiply the
- * pieces on MFMA with FP32 accumulation and recombine in FP64. */
+/* Arithmetic of the real GEMMs.  FP64: FP64 MFMA.  The split forms (an
+ * Ozaki-style scheme; the paper itself uses FP64 throughout, Sec. III A)
+ * write every FP64 operand as `slices` signed integer digits of beta bits
+ * under a power-of-two exponent per row (left operand) or column (right
+ * operand), multiply digit slices on low-precision MFMA with exact FP32
+ * (BF16, FP8) or int32 (INT8) sums, keep the slice pairs with s + t <=
+ * slices + 1, and accumulate and rescale in FP64.  Digit types: BF16
+ * (beta 7, slices 1..8, default 7), OCP FP8 E4M3 (beta 4, slices 1..14,
+ * default 13), INT8 (beta 6, slices 1..9, default 8).  The Hadamard and
+ * Gauss pre-combinations and the post-combination stay FP64. */
 typedef enum {
   BQ_PREC_FP64 = 0,
   BQ_PREC_SPLIT_BF16 = 1,
-  BQ_PREC_SPLIT_FP8 = 2
+  BQ_PREC_SPLIT_FP8 = 2,
+  BQ_PREC_SPLIT_INT8 = 3
 } bq_prec_t;
 
 typedef struct bq_handle_s* bq_handle_t;
@@ -150,7 +157,10 @@ typedef enum {
   BQ_KERNEL_GEMM_CR = 2,    /* complex x real, 2 real products       */
   BQ_KERNEL_GEMM_RR = 3,    /* real x real, 1 real product           */
   BQ_KERNEL_COMBINE = 10,   /* Hadamard pre-combination              */
-  BQ_KERNEL_FILL = 11       /* zero fill of a structurally zero block */
+  BQ_KERNEL_FILL = 11,      /* zero fill of a structurally zero block */
+  BQ_KERNEL_SPLIT = 12,     /* exponents + digit slices of one operand */
+  BQ_KERNEL_SLICE_GEMM = 13 /* one real product from digit slices;
+                               flops = pairs * 2 m n k, config = slices */
 } bq_kernel_t;
 
 typedef struct {

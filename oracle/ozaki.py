@@ -1,0 +1,60 @@
+"""Oracle for the split-precision (Ozaki-style) real product.
+
+TEST INFRASTRUCTURE: used only by tests; shares no code with the HIP path.
+
+The paper computes every real GEMM in FP64; the split form is an extension
+(error-free splitting of Ozaki, Ogita, Oishi and Rump, 2012), read here as:
+
+* left factor X (m x k): per row i an exponent e_i, the frexp exponent of
+  max_j |x_ij| (so |x_ij| 2^-e_i < 1); right factor Y (k x n): per column j
+  an exponent f_j;
+* digits of y = x 2^-e: q_1 = rint(2^b y), y_1 = y - q_1 2^-b, and
+  q_s = rint(2^{bs} y_{s-1}), y_s = y_{s-1} - q_s 2^{-bs} for s = 2..S;
+* T = diag(2^e) [ sum_{s + t <= S + 1} 2^{-b(s+t)} Q_s R_t ] diag(2^f).
+
+Digit products are exact integers here (int64); the sum over s + t is taken
+in FP64 level by level.  The result therefore differs from the GPU split
+path only by FP64 summation order.
+"""
+import numpy as np
+
+BETA = {"bf16": 7, "fp8": 4, "int8": 6}
+
+
+def exponents(X, axis):
+    """frexp exponent of the largest magnitude along `axis` (rows: axis=1);
+    all-zero lines get None (their digits are zero)."""
+    mx = np.max(np.abs(X), axis=axis)
+    _, e = np.frexp(mx)
+    return np.where(mx > 0, e, 0).astype(np.int64), mx > 0
+
+
+def digits(X, beta, S, axis):
+    """Digit slices Q[s] (int64) and exponents of X along `axis`
+    (axis=1: one exponent per row, the left factor; axis=0: per column)."""
+    X = np.asarray(X, dtype=np.float64)
+    e, nz = exponents(X, axis)
+    ee = e[:, None] if axis == 1 else e[None, :]
+    y = np.ldexp(X, -ee)
+    Q = []
+    for s in range(1, S + 1):
+        q = np.rint(np.ldexp(y, beta * s))
+        y = y - np.ldexp(q, -beta * s)
+        Q.append(q.astype(np.int64))
+    return Q, e, y  # y: remainder (scaled)
+
+
+def product(X, Y, kind="bf16", S=7):
+    """Split-form real product X @ Y."""
+    beta = BETA[kind]
+    QX, ex, _ = digits(X, beta, S, axis=1)
+    QY, ey, _ = digits(Y, beta, S, axis=0)
+    acc = np.zeros((X.shape[0], Y.shape[1]), dtype=np.float64)
+    for d in range(2, S + 2):
+        lvl = np.zeros_like(acc, dtype=np.int64)
+        for s in range(1, d):
+            t = d - s
+            if s <= S and t <= S:
+                lvl += QX[s - 1] @ QY[t - 1]
+        acc = acc + np.ldexp(lvl.astype(np.float64), -beta * d)
+    return np.ldexp(np.ldexp(acc, ex[:, None]), ey[None, :])

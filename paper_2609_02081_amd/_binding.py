@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbq.so")
 
 OPS = {"N": 0, "T": 1, "C": 2, "H": 3}
-PRECS = {"fp64": 0, "split_bf16": 1, "split_fp8": 2}
+PRECS = {"fp64": 0, "split_bf16": 1, "split_fp8": 2, "split_int8": 3}
 STATUS = {0: "BQ_OK", 1: "BQ_ERR_INVALID_VALUE", 2: "BQ_ERR_UNSUPPORTED", 3: "BQ_ERR_ALIAS",
           4: "BQ_ERR_WORKSPACE", 5: "BQ_ERR_HIP", 6: "BQ_ERR_ARCH"}
 
@@ -31,7 +31,8 @@ class BqTraceRecord(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-KERNEL_NAMES = {0: "gemm_gauss", 1: "gemm_rc", 2: "gemm_cr", 3: "gemm_rr", 10: "combine", 11: "fill"}
+KERNEL_NAMES = {0: "gemm_gauss", 1: "gemm_rc", 2: "gemm_cr", 3: "gemm_rr", 10: "combine", 11: "fill",
+                12: "split", 13: "slice_gemm"}
 
 
 class BqError(RuntimeError):

@@ -178,25 +178,76 @@ Plan make_plan(const Problem& P) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Workspace: pre-combined operands of P5..P8 (packed, ld = cols).
-void workspace_need(const Plan& pl, int64_t m, int64_t n, int64_t k, size_t* resident, size_t* minimum) {
-  if (!pl.bilinear || m == 0 || n == 0 || k == 0) {
-    *resident = 0;
-    *minimum = 0;
-    return;
-  }
+// Arithmetic of the real GEMMs: et = -1 FP64 MFMA, else the digit type of
+// the split form (0 BF16, 1 FP8, 2 INT8) with S slices.
+struct Prec {
+  int et = -1;
+  int S = 0;
+};
+
+constexpr int kDefaultSlices[3] = {7, 13, 8};
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Digit buffers of one split real product (reused by every real product).
+struct SplitLayout {
+  int64_t rows_pad, cols_pad, kp;
+  size_t a_bytes, b_bytes, ea_bytes, eb_bytes;
+  size_t total() const { return a_bytes + b_bytes + ea_bytes + eb_bytes; }
+};
+
+SplitLayout split_layout(const Prec& pr, int64_t m, int64_t n, int64_t k) {
+  SplitLayout L{};
+  const int es = pr.et == 0 ? 2 : 1;
+  L.rows_pad = round_up(m, 128);
+  L.cols_pad = round_up(n, 64);
+  L.kp = round_up(k, 64);
+  L.a_bytes = align256(size_t(pr.S) * size_t(L.rows_pad) * size_t(L.kp) * es);
+  L.b_bytes = align256(size_t(pr.S) * size_t(L.cols_pad) * size_t(L.kp) * es);
+  L.ea_bytes = align256(size_t(L.rows_pad) * 4);
+  L.eb_bytes = align256(size_t(L.cols_pad) * 4);
+  return L;
+}
+
+// Workspace: pre-combined operands of P5..P8 (packed, ld = cols), plus the
+// digit buffers of one real product in the split form.
+void workspace_need(const Plan& pl, const Prec& pr, int64_t m, int64_t n, int64_t k, size_t* resident,
+                    size_t* minimum) {
+  *resident = 0;
+  *minimum = 0;
+  if (m == 0 || n == 0 || k == 0) return;
+  const size_t split = pr.et >= 0 ? split_layout(pr, m, n, k).total() : 0;
   bool any = false;
   for (const Prod& p : pl.prods) any |= (p.L.combo >= 0);
-  if (!any) {
-    *resident = 0;
-    *minimum = 0;
-    return;
+  if (pl.bilinear && any) {
+    const size_t a1 = align256(size_t(m) * size_t(k) * 8);
+    const size_t b1 = align256(size_t(k) * size_t(n) * 8);
+    const size_t per_q = (pl.combA_r + pl.combA_i) * a1 + (pl.combB_r + pl.combB_i) * b1;
+    *resident = 4 * per_q;
+    *minimum = per_q;
   }
-  const size_t a1 = align256(size_t(m) * size_t(k) * 8);
-  const size_t b1 = align256(size_t(k) * size_t(n) * 8);
-  const size_t per_q = (pl.combA_r + pl.combA_i) * a1 + (pl.combB_r + pl.combB_i) * b1;
-  *resident = 4 * per_q;
-  *minimum = per_q;
+  *resident += split;
+  *minimum += split;
+}
+
+bq_status_t prec_of(bq_prec_t prec, int slices, Prec* out) {
+  Prec p;
+  switch (prec) {
+    case BQ_PREC_FP64: p.et = -1; break;
+    case BQ_PREC_SPLIT_BF16: p.et = 0; break;
+    case BQ_PREC_SPLIT_FP8: p.et = 1; break;
+    case BQ_PREC_SPLIT_INT8: p.et = 2; break;
+    default: return fail(BQ_ERR_INVALID_VALUE, "unknown precision");
+  }
+  if (slices < 0) return fail(BQ_ERR_INVALID_VALUE, "slices must be >= 0");
+  if (p.et >= 0) {
+    p.S = slices == 0 ? kDefaultSlices[p.et] : slices;
+    if (p.S > bq::max_slices(p.et))
+      return fail(BQ_ERR_INVALID_VALUE, "slices above " + std::to_string(bq::max_slices(p.et)) +
+                                            " for this digit type");
+  }
+  *out = p;
+  return BQ_OK;
 }
 
 Problem problem_of(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B) {
@@ -233,13 +284,12 @@ bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) !=
 // call writes (all of them must be non-null).
 bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
                      const bq_matrix_t* C, bq_prec_t prec, int slices, const void* ws,
-                     size_t ws_bytes, unsigned out_mask, Plan* plan_out, bool* streamed) {
+                     size_t ws_bytes, unsigned out_mask, Plan* plan_out, bool* streamed, Prec* prec_out) {
   if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
   auto op_ok = [](bq_op_t o) { return o == BQ_OP_N || o == BQ_OP_T || o == BQ_OP_C || o == BQ_OP_H; };
   if (!op_ok(opA) || !op_ok(opB)) return fail(BQ_ERR_INVALID_VALUE, "op must be N, T, C or H");
-  if (prec != BQ_PREC_FP64 && prec != BQ_PREC_SPLIT_BF16 && prec != BQ_PREC_SPLIT_FP8)
-    return fail(BQ_ERR_INVALID_VALUE, "unknown precision");
-  if (slices < 0) return fail(BQ_ERR_INVALID_VALUE, "slices must be >= 0");
+  Prec pr;
+  if (bq_status_t ps = prec_of(prec, slices, &pr); ps != BQ_OK) return ps;
   const bq_matrix_t* M[3] = {A, B, C};
   const char* nm[3] = {"A", "B", "C"};
   for (int t = 0; t < 3; ++t) {
@@ -265,13 +315,12 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
         return fail(BQ_ERR_INVALID_VALUE, "output component " + std::to_string(c) + " is null");
   if (opA == BQ_OP_T || opA == BQ_OP_H || opB == BQ_OP_T || opB == BQ_OP_H)
     return fail(BQ_ERR_UNSUPPORTED, "op T and H are not implemented in this build");
-  if (prec != BQ_PREC_FP64) return fail(BQ_ERR_UNSUPPORTED, "split precision is not implemented in this build");
   if (ws_bytes > 0 && !ws) return fail(BQ_ERR_INVALID_VALUE, "ws is null but ws_bytes > 0");
 
   const int64_t m = A->rows, n = B->cols, k = A->cols;
   Plan plan = make_plan(problem_of(opA, opB, A, B));
   size_t res = 0, mn = 0;
-  workspace_need(plan, m, n, k, &res, &mn);
+  workspace_need(plan, pr, m, n, k, &res, &mn);
   if (ws_bytes < mn)
     return fail(BQ_ERR_WORKSPACE, "workspace " + std::to_string(ws_bytes) + " B < minimum " + std::to_string(mn) + " B");
   const char* fs = std::getenv("BQ_FORCE_STREAMED");
@@ -304,6 +353,7 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
   }
   if (plan_out) *plan_out = std::move(plan);
   if (streamed) *streamed = use_stream;
+  if (prec_out) *prec_out = pr;
   return BQ_OK;
 }
 
@@ -318,6 +368,14 @@ void tile_order(int* xcd, int* group) {
     *xcd = a != 0;
     *group = b;
   }
+}
+
+// Slice-GEMM block shape (BQ_SLICE_VARIANT = 0 or 1 overrides the default).
+int slice_variant() {
+  const char* e = std::getenv("BQ_SLICE_VARIANT");
+  if (!e || !*e) return -1;
+  const int v = std::atoi(e);
+  return (v == 0 || v == 1) ? v : -1;
 }
 
 int tile_override() {
@@ -362,8 +420,8 @@ struct Tracer {
 };
 
 // Enqueue the plan.  Validation has passed.
-bq_status_t execute(bq_handle_t h, const Plan& pl, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C,
-                    unsigned out_mask, void* ws, bool streamed, hipStream_t s) {
+bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matrix_t* A, const bq_matrix_t* B,
+                    bq_matrix_t* C, unsigned out_mask, void* ws, bool streamed, hipStream_t s) {
   const int64_t m = A->rows, n = B->cols, k = A->cols;
   if (m == 0 || n == 0) return BQ_OK;
   bool touched[8] = {};
@@ -384,6 +442,71 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const bq_matrix_t* A, const b
     if (pl.combB_r) { cB_r[q] = reinterpret_cast<double*>(wp); wp += b1; }
     if (pl.combB_i) { cB_i[q] = reinterpret_cast<double*>(wp); wp += b1; }
   }
+  // Digit buffers of the split form.
+  SplitLayout sl{};
+  void* dig_a = nullptr;
+  void* dig_b = nullptr;
+  int* exp_a = nullptr;
+  int* exp_b = nullptr;
+  if (pr.et >= 0 && k > 0) {
+    sl = split_layout(pr, m, n, k);
+    dig_a = wp; wp += sl.a_bytes;
+    dig_b = wp; wp += sl.b_bytes;
+    exp_a = reinterpret_cast<int*>(wp); wp += sl.ea_bytes;
+    exp_b = reinterpret_cast<int*>(wp); wp += sl.eb_bytes;
+  }
+  const int es = pr.et == 0 ? 2 : 1;
+  const int beta = pr.et == 0 ? 7 : (pr.et == 1 ? 4 : 6);
+
+  // One real product T = X Y of the split form, X = xw1 x1 + xw2 x2 (m x k),
+  // Y = yw1 y1 + yw2 y2 (k x n); C_w op= cw * T for each (w, cw).
+  auto split_product = [&](const double* x1, double xw1, const double* x2, double xw2, int64_t ldx,
+                           const double* y1, double yw1, const double* y2, double yw2, int64_t ldy,
+                           const std::vector<std::pair<int, double>>& outs) -> hipError_t {
+    bq::SliceGemmArgs sg{};
+    for (const auto& o : outs) {
+      if (!(out_mask >> o.first & 1) || o.second == 0.0) continue;
+      sg.c[sg.ntgt] = C->comp[o.first];
+      sg.coef[sg.ntgt] = o.second;
+      sg.mode[sg.ntgt] = touched[o.first] ? bq::TGT_ACCUM : bq::TGT_WRITE;
+      touched[o.first] = true;
+      ++sg.ntgt;
+    }
+    if (sg.ntgt == 0) return hipSuccess;
+    bq::SplitArgs xa{x1, x2, xw1, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp, sl.rows_pad * sl.kp, beta, 1};
+    bq::SplitArgs ya{y1, y2, yw1, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp, sl.cols_pad * sl.kp, beta, 0};
+    const double elems_x = double(m) * double(k), elems_y = double(k) * double(n);
+    {
+      Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
+                elems_x * 8.0 * (x2 ? 2 : 1) * 2.0 + double(sl.rows_pad) * double(sl.kp) * pr.S * es);
+      hipError_t e = bq::launch_split(pr.et, pr.S, xa, exp_a, dig_a, s);
+      tr.done();
+      if (e != hipSuccess) return e;
+    }
+    {
+      Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, k, n, 0, 0.0,
+                elems_y * 8.0 * (y2 ? 2 : 1) * 2.0 + double(sl.cols_pad) * double(sl.kp) * pr.S * es);
+      hipError_t e = bq::launch_split(pr.et, pr.S, ya, exp_b, dig_b, s);
+      tr.done();
+      if (e != hipSuccess) return e;
+    }
+    sg.a = dig_a;
+    sg.b = dig_b;
+    sg.slice_stride_a = sl.rows_pad * sl.kp;
+    sg.slice_stride_b = sl.cols_pad * sl.kp;
+    sg.kp = sl.kp;
+    sg.ea = exp_a;
+    sg.eb = exp_b;
+    sg.m = m;
+    sg.n = n;
+    sg.beta = beta;
+    sg.ldc = C->ld;
+    const double pairs = double(pr.S) * double(pr.S + 1) / 2.0;
+    Tracer tr(h, s, BQ_KERNEL_SLICE_GEMM, pr.S, m, n, k, pairs * 2.0 * double(m) * double(n) * double(k), 0.0);
+    hipError_t e = bq::launch_slice_gemm(pr.et, pr.S, slice_variant(), sg, s);
+    tr.done();
+    return e;
+  };
 
   auto combine = [&](bool left, int q0, int nq, int slot0) -> hipError_t {
     bq::CombineArgs ca{};
@@ -443,6 +566,44 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const bq_matrix_t* A, const b
     else kind = bq::KIND_RR;
     const bool pr_nz = true;
     const bool pi_nz = (kind != bq::KIND_RR);
+
+    if (pr.et >= 0) {
+      // Split form: the complex product as its real products, each added into
+      // C with the coefficients it carries through P_R, P_I and the targets.
+      struct RealProd {
+        const double *x1, *x2;
+        double xw2;
+        const double *y1, *y2;
+        double yw2;
+        double aR, aI;  // P_R += aR T, P_I += aI T
+      };
+      std::vector<RealProd> rps;
+      const double sig = L.s * R.s;
+      if (kind == bq::KIND_GAUSS) {
+        rps.push_back({L.r, nullptr, 0.0, R.r, nullptr, 0.0, 1.0, -1.0});
+        rps.push_back({L.i, nullptr, 0.0, R.i, nullptr, 0.0, -sig, -sig});
+        rps.push_back({L.r, L.i, L.s, R.r, R.i, R.s, 0.0, 1.0});
+      } else if (kind == bq::KIND_RC) {
+        rps.push_back({L.r, nullptr, 0.0, R.r, nullptr, 0.0, 1.0, 0.0});
+        rps.push_back({L.r, nullptr, 0.0, R.i, nullptr, 0.0, 0.0, R.s});
+      } else if (kind == bq::KIND_CR) {
+        rps.push_back({L.r, nullptr, 0.0, R.r, nullptr, 0.0, 1.0, 0.0});
+        rps.push_back({L.i, nullptr, 0.0, R.r, nullptr, 0.0, 0.0, L.s});
+      } else {
+        rps.push_back({L.r, nullptr, 0.0, R.r, nullptr, 0.0, 1.0, 0.0});
+      }
+      for (const RealProd& rp : rps) {
+        std::vector<std::pair<int, double>> outs;
+        for (const Tgt& t : p.tgts) {
+          const Cplx c = cmul(t.coef, rot);
+          outs.push_back({t.w, c.re * rp.aR - c.im * rp.aI});
+          outs.push_back({t.w + 4, c.re * rp.aI + c.im * rp.aR});
+        }
+        hipError_t e = split_product(rp.x1, 1.0, rp.x2, rp.xw2, L.ld, rp.y1, 1.0, rp.y2, rp.yw2, R.ld, outs);
+        if (e != hipSuccess) return hip_fail(e, "split-precision launch");
+      }
+      continue;
+    }
 
     bq::GemmArgs g{};
     g.lr = L.r; g.li = L.i; g.lda = L.ld;
@@ -508,12 +669,13 @@ bq_status_t run(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, c
                 bq_stream_t stream) {
   if (!h) return fail(BQ_ERR_INVALID_VALUE, "handle is null");
   Plan plan;
+  Prec pr;
   bool streamed = false;
-  bq_status_t st = validate(opA, opB, A, B, C, prec, slices, ws, ws_bytes, out_mask, &plan, &streamed);
+  bq_status_t st = validate(opA, opB, A, B, C, prec, slices, ws, ws_bytes, out_mask, &plan, &streamed, &pr);
   if (st != BQ_OK) return st;
   st = check_handle(h);
   if (st != BQ_OK) return st;
-  return execute(h, plan, A, B, C, out_mask, ws, streamed, static_cast<hipStream_t>(stream));
+  return execute(h, plan, pr, A, B, C, out_mask, ws, streamed, static_cast<hipStream_t>(stream));
 }
 
 bq_matrix_t restrict_to(const bq_matrix_t* X, unsigned mask) {
@@ -602,9 +764,8 @@ bq_status_t bq_gemm_workspace_size(int64_t m, int64_t n, int64_t k, unsigned mas
                                    bq_prec_t prec, int slices, size_t* resident_bytes, size_t* min_bytes) {
   if (m < 0 || n < 0 || k < 0) return fail(BQ_ERR_INVALID_VALUE, "negative dimension");
   if (maskA > 0xFFu || maskB > 0xFFu) return fail(BQ_ERR_INVALID_VALUE, "mask has bits above 7");
-  if (prec != BQ_PREC_FP64 && prec != BQ_PREC_SPLIT_BF16 && prec != BQ_PREC_SPLIT_FP8)
-    return fail(BQ_ERR_INVALID_VALUE, "unknown precision");
-  if (slices < 0) return fail(BQ_ERR_INVALID_VALUE, "slices must be >= 0");
+  Prec pr;
+  if (bq_status_t ps = prec_of(prec, slices, &pr); ps != BQ_OK) return ps;
   Problem P{};
   P.m = m; P.n = n; P.k = k;
   const double* present = kCombo;
@@ -616,7 +777,7 @@ bq_status_t bq_gemm_workspace_size(int64_t m, int64_t n, int64_t k, unsigned mas
   P.ldb = std::max<int64_t>(1, n);
   Plan pl = make_plan(P);
   size_t res = 0, mn = 0;
-  workspace_need(pl, m, n, k, &res, &mn);
+  workspace_need(pl, pr, m, n, k, &res, &mn);
   if (resident_bytes) *resident_bytes = res;
   if (min_bytes) *min_bytes = mn;
   return BQ_OK;
@@ -635,7 +796,7 @@ int bq_plan_real_gemms(unsigned maskA, unsigned maskB) {
 
 bq_status_t bq_gemm_check(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
                           const bq_matrix_t* C, bq_prec_t prec, int slices, const void* ws, size_t ws_bytes) {
-  return validate(opA, opB, A, B, C, prec, slices, ws, ws_bytes, 0xFFu, nullptr, nullptr);
+  return validate(opA, opB, A, B, C, prec, slices, ws, ws_bytes, 0xFFu, nullptr, nullptr, nullptr);
 }
 
 bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,

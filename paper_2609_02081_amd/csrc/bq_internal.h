@@ -64,6 +64,43 @@ struct CombineArgs {
   int64_t rows, cols;
 };
 
+// One real FP64 operand to be split into low-precision digit slices:
+// value = w1 * s1 + w2 * s2 (s2 may be null), row-major with leading
+// dimension ld.  left: the operand is the left factor (m x k, one exponent
+// per row, digits D[s][row][kk]); otherwise the right factor (k x n, one
+// exponent per column, digits stored transposed, D[s][col][kk]).
+struct SplitArgs {
+  const double* s1;
+  const double* s2;
+  double w1, w2;
+  int64_t ld;
+  int64_t rows, cols;          // source shape
+  int64_t rows_pad, cols_pad;  // left: rows padded to 128; right: cols padded to 64
+  int64_t kp;                  // reduced dimension padded to 64 (zero digits)
+  int64_t slice_stride;        // elements between consecutive slices
+  int beta;                    // digit width in bits
+  int left;
+};
+
+constexpr int kMaxSliceTargets = 8;
+
+// T = X Y from digit slices; coef[q] * T is stored (TGT_WRITE) or added
+// (TGT_ACCUM) into c[q] (m x n, leading dimension ldc).
+struct SliceGemmArgs {
+  const void* a;  // left digits  [S][rows_pad][kp]
+  const void* b;  // right digits [S][cols_pad][kp]
+  int64_t slice_stride_a, slice_stride_b, kp;
+  const int* ea;  // row exponents of the left operand
+  const int* eb;  // column exponents of the right operand
+  int64_t m, n;
+  int beta;
+  int ntgt;
+  double* c[kMaxSliceTargets];
+  double coef[kMaxSliceTargets];
+  int mode[kMaxSliceTargets];
+  int64_t ldc;
+};
+
 struct TileConfig {
   int bm, bn, bk, wm, wn;
 };
@@ -75,5 +112,12 @@ hipError_t launch_fill_zero(double* p, int64_t rows, int64_t cols, int64_t ld, h
 int num_tile_configs();
 TileConfig tile_config(int cfg);
 int default_tile_config(int kind, int64_t m, int64_t n, int64_t k);
+// Split-precision kernels (bq_split.hip).  et: 0 = BF16 digits (beta 7),
+// 1 = OCP FP8 E4M3 digits (beta 4), 2 = INT8 digits (beta 6).
+hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t s);
+hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t s);  // variant -1: default
+int max_slices(int et);
+int slice_block_rows(int et, int S);  // rows of a slice-GEMM block tile (128 or 64)
+int slice_kstep(int et);              // k per MFMA step (32 or 64)
 
 }  // namespace bq

@@ -1,0 +1,555 @@
+// Split-precision real GEMM (Ozaki-style) for gfx950.
+//
+// A real FP64 product T = X Y (X m x k, Y k x n) is computed from
+// low-precision slices:
+//   * every row i of X gets a power-of-two exponent e_i (the frexp exponent
+//     of its largest magnitude), every column j of Y an exponent f_j;
+//   * x_ij 2^-e_i in (-1, 1) is written as S signed digits,
+//     q_1 = rint(2^b y), y_1 = y - q_1 2^-b, q_s = rint(2^{bs} y_{s-1}), ...
+//     so x = 2^e_i (sum_s q_s 2^{-bs} + remainder), |q_1| <= 2^b,
+//     |q_s| <= 2^{b-1}; the digits are small integers, exact in BF16 (b = 7),
+//     OCP FP8 E4M3 (b = 4) or INT8 (b = 6);
+//   * T_ij = 2^{e_i + f_j} sum_{d = 2}^{S+1} 2^{-bd} sum_{s + t = d} (Q_s R_t)_ij
+//     (pairs with s + t > S + 1 are dropped).
+// Each level d is accumulated by MFMA over one k-step (32 deep in FP32 for
+// BF16/FP8: at most S * 32 * 2^{2b} < 2^24, so every partial sum is an exact
+// integer; 64 deep in int32 for INT8) and then added, scaled by 2^{-bd},
+// into FP64 accumulators.  Only
+// the splitting, the exponent scaling and the level accumulation are FP64.
+#include <limits.h>
+
+#include "bq_internal.h"
+
+namespace bq {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4s __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i2v __attribute__((ext_vector_type(2)));
+
+// Value of the split operand: w1 * s1 + w2 * s2 (s2 may be absent).  The
+// FP64 path forms its Gauss sums with the same single rounding.
+__device__ __forceinline__ double operand_value(const SplitArgs& a, int64_t off) {
+  const double x = a.s1[off];
+  return a.s2 ? __builtin_fma(a.w2, a.s2[off], a.w1 * x) : a.w1 * x;
+}
+
+__device__ __forceinline__ int exp_of(double x) {
+  int e;
+  (void)frexp(x, &e);
+  return x == 0.0 ? INT_MIN : e;
+}
+
+// Exponents: e[r] = max over the reduced dimension of frexp exponents
+// (rows of the left operand, columns of the right one).  exps must hold
+// INT_MIN beforehand.  Block: 256 threads.
+__global__ void __launch_bounds__(256) split_exp_left(const SplitArgs a, int* exps) {
+  // grid.x = rows, grid.y = chunks of 2048 columns
+  const int64_t r = blockIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * 2048;
+  int e = INT_MIN;
+  for (int j = threadIdx.x; j < 2048; j += 256) {
+    const int64_t c = c0 + j;
+    if (c < a.cols) e = max(e, exp_of(operand_value(a, r * a.ld + c)));
+  }
+  for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    e = max(max(red[0], red[1]), max(red[2], red[3]));
+    if (e != INT_MIN) atomicMax(&exps[r], e);
+  }
+}
+
+__global__ void __launch_bounds__(256) split_exp_right(const SplitArgs a, int* exps) {
+  // grid.x = column blocks of 64, grid.y = row blocks of 1024; thread: one
+  // column, every 4th row of the block.
+  const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t r0 = (int64_t)blockIdx.y * 1024 + (threadIdx.x >> 6);
+  int e = INT_MIN;
+  if (c < a.cols)
+    for (int64_t r = r0; r < a.rows && r < (int64_t)(blockIdx.y + 1) * 1024; r += 4)
+      e = max(e, exp_of(operand_value(a, r * a.ld + c)));
+  __shared__ int red[256];
+  red[threadIdx.x] = e;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    e = max(max(red[threadIdx.x], red[threadIdx.x + 64]), max(red[threadIdx.x + 128], red[threadIdx.x + 192]));
+    if (c < a.cols && e != INT_MIN) atomicMax(&exps[c], e);
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_int(int* p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Digits of one element: q[0..S-1] from x and its row/column exponent.
+template <int S>
+__device__ __forceinline__ void digits(double x, int e, int beta, float* q) {
+  double y = (e == INT_MIN) ? 0.0 : ldexp(x, -e);
+#pragma unroll
+  for (int s = 1; s <= S; ++s) {
+    const double d = rint(ldexp(y, beta * s));
+    q[s - 1] = (float)d;
+    y = y - ldexp(d, -beta * s);
+  }
+}
+
+// Small integer (|q| <= 256) to BF16 bits: exact truncation of the FP32 bits.
+__device__ __forceinline__ unsigned short to_bf16(float q) {
+  return (unsigned short)(__float_as_uint(q) >> 16);
+}
+
+// INT8 digits (beta 6) are stored as two's-complement bytes (|q| <= 64).
+// Small integer (|q| <= 16) to OCP FP8 E4M3 bits.
+__device__ __forceinline__ unsigned char to_e4m3(float qf) {
+  int q = (int)qf;
+  const unsigned char s = q < 0 ? 0x80 : 0;
+  q = q < 0 ? -q : q;
+  if (q == 0) return 0;
+  const int E = 31 - __clz(q);
+  const int mant = ((q << 3) >> E) & 7;
+  return (unsigned char)(s | ((E + 7) << 3) | mant);
+}
+
+// Left operand: digits D[s][r][kk] (kk < kp, rows < rows_pad; zero padding).
+// Thread: 8 consecutive kk of one row.  grid.x = rows_pad, grid.y = kp / 2048.
+template <int ET, int S>
+__global__ void __launch_bounds__(256) split_digits_left(const SplitArgs a, const int* exps, void* out) {
+  const int64_t r = blockIdx.x;
+  const int64_t kk0 = (int64_t)blockIdx.y * 2048 + threadIdx.x * 8;
+  if (kk0 >= a.kp) return;
+  const int e = (r < a.rows) ? exps[r] : INT_MIN;
+  float q[8][S];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t c = kk0 + t;
+    const double x = (r < a.rows && c < a.cols) ? operand_value(a, r * a.ld + c) : 0.0;
+    digits<S>(x, e, a.beta, q[t]);
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int64_t o = (int64_t)s * a.slice_stride + r * a.kp + kk0;
+    if constexpr (ET == 0) {
+      i4v v;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        v[t] = (int)to_bf16(q[2 * t][s]) | ((int)to_bf16(q[2 * t + 1][s]) << 16);
+      *reinterpret_cast<i4v*>(static_cast<unsigned short*>(out) + o) = v;
+    } else if constexpr (ET == 2) {
+      i2v v;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        v[t] = (int)(unsigned char)(signed char)q[4 * t][s] | ((int)(unsigned char)(signed char)q[4 * t + 1][s] << 8) |
+               ((int)(unsigned char)(signed char)q[4 * t + 2][s] << 16) |
+               ((int)(unsigned char)(signed char)q[4 * t + 3][s] << 24);
+      *reinterpret_cast<i2v*>(static_cast<unsigned char*>(out) + o) = v;
+    } else {
+      i2v v;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        v[t] = (int)to_e4m3(q[4 * t][s]) | ((int)to_e4m3(q[4 * t + 1][s]) << 8) |
+               ((int)to_e4m3(q[4 * t + 2][s]) << 16) | ((int)to_e4m3(q[4 * t + 3][s]) << 24);
+      *reinterpret_cast<i2v*>(static_cast<unsigned char*>(out) + o) = v;
+    }
+  }
+}
+
+// Right operand (k x n, row-major): digits stored transposed, D[s][c][kk].
+// Block: a 64 (kk) x 64 (c) tile through LDS.  grid.x = cols_pad / 64,
+// grid.y = kp / 64.
+template <int ET, int S>
+__global__ void __launch_bounds__(256) split_digits_right(const SplitArgs a, const int* exps, void* out) {
+  constexpr int ES = ET == 0 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) unsigned char tile[S][64][64 * ES + 16];
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  const int64_t k0 = (int64_t)blockIdx.y * 64;
+  const int tc = threadIdx.x & 63;
+  const int64_t c = c0 + tc;
+  const int e = (c < a.cols) ? exps[c] : INT_MIN;
+  for (int rr = threadIdx.x >> 6; rr < 64; rr += 4) {
+    const int64_t kk = k0 + rr;
+    const double x = (c < a.cols && kk < a.rows) ? operand_value(a, kk * a.ld + c) : 0.0;
+    float q[S];
+    digits<S>(x, e, a.beta, q);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if constexpr (ET == 0)
+        *reinterpret_cast<unsigned short*>(&tile[s][tc][rr * 2]) = to_bf16(q[s]);
+      else if constexpr (ET == 2)
+        tile[s][tc][rr] = (unsigned char)(signed char)q[s];
+      else
+        tile[s][tc][rr] = to_e4m3(q[s]);
+    }
+  }
+  __syncthreads();
+  // Write: row c of slice s gets 64 * ES contiguous bytes; 16-byte pieces.
+  constexpr int PIECES = 64 * ES / 16;  // 8 (bf16) or 4 (fp8)
+  for (int w = threadIdx.x; w < S * 64 * PIECES; w += 256) {
+    const int s = w / (64 * PIECES);
+    const int rem = w % (64 * PIECES);
+    const int cc = rem / PIECES, p = rem % PIECES;
+    const i4v v = *reinterpret_cast<const i4v*>(&tile[s][cc][p * 16]);
+    unsigned char* dst = static_cast<unsigned char*>(out) +
+                         ((int64_t)s * a.slice_stride + (c0 + cc) * a.kp + k0) * ES + p * 16;
+    *reinterpret_cast<i4v*>(dst) = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Slice GEMM.  A 128 x 64 block tile (8 waves of 32 x 32, or 4 waves of
+// 64 x 32 for many slices), one MFMA k-step per LDS stage.  LDS holds all S slices of the A and B
+// tiles of that k-step; 16-byte (BF16, INT8) or 8-byte (FP8) chunks are
+// XOR-swizzled per row so fragment reads are free of bank conflicts.
+//
+// MFMA layouts (checked with one-wave probes on gfx950):
+//   A: lane l holds row l % 16, k = E (l / 16) .. +E-1   (E elements/lane)
+//   B: lane l holds column l % 16, same k
+//   D: lane l, element v holds row 4 (l / 16) + v, column l % 16.
+// ---------------------------------------------------------------------------
+template <int ET>
+struct SliceTraits;
+template <>
+struct SliceTraits<0> {  // BF16 digits, v_mfma_f32_16x16x32_bf16
+  static constexpr int ES = 1 * 2, KSTEP = 32, CH = 16, BETA = 7;
+  typedef bf16x8 frag_t;
+  typedef f4 acc_t;
+  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct SliceTraits<1> {  // OCP FP8 E4M3 digits, v_mfma_f32_16x16x32_fp8_fp8
+  static constexpr int ES = 1, KSTEP = 32, CH = 8, BETA = 4;
+  typedef long frag_t;
+  typedef f4 acc_t;
+  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct SliceTraits<2> {  // INT8 digits, v_mfma_i32_16x16x64_i8 (exact int32 sums)
+  static constexpr int ES = 1, KSTEP = 64, CH = 16, BETA = 6;
+  typedef i4v frag_t;
+  typedef i4v acc_t;
+  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr double pow2neg(int e) { return 1.0 / (double)(1ull << e); }
+
+template <int ET, int S, int WM, int MI, int CACHE_B, int NSTAGE, int WPE>
+__global__ void __launch_bounds__(WM * 2 * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+slice_gemm(const SliceGemmArgs g) {
+  typedef SliceTraits<ET> Tr;
+  typedef typename Tr::frag_t frag_t;
+  typedef typename Tr::acc_t acc_t;
+  constexpr int ES = Tr::ES, BK = Tr::KSTEP, CH = Tr::CH, BETA = Tr::BETA;
+  constexpr int NT = WM * 2 * 64;
+  constexpr int NI = 2;                // wave tile: (16 MI) x 32
+  constexpr int BM = 16 * MI * WM, BN = 64;
+  constexpr int ROWB = BK * ES;        // bytes per tile row: 64 (BF16, INT8) or 32 (FP8)
+  constexpr int NCH = ROWB / CH;       // chunks per row: 4
+  constexpr int A_BYTES = S * BM * ROWB;
+  constexpr int B_BYTES = S * BN * ROWB;
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int A_LD_TOTAL = A_BYTES / 16;  // 16-byte pieces per k-step
+  constexpr int A_LD = (A_LD_TOTAL + NT - 1) / NT;
+  constexpr int B_LD_TOTAL = B_BYTES / 16;
+  constexpr int B_LD = (B_LD_TOTAL + NT - 1) / NT;
+  static_assert(NCH == 4, "four chunks per row");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[NSTAGE * STAGE];
+
+  const int tiles_m = (int)((g.m + BM - 1) / BM);
+  const int tiles_n = (int)((g.n + BN - 1) / BN);
+  // XCD-aware grouped tile order (as in the FP64 GEMM).
+  int tm, tn;
+  {
+    const int T = tiles_m * tiles_n, w = blockIdx.x;
+    const int x = w % 8, slot = w / 8, base = T / 8, rem = T % 8;
+    const int t = x * base + (x < rem ? x : rem) + slot;
+    const int per_group = 8 * tiles_n, group = t / per_group, first_m = group * 8;
+    const int gm = min(tiles_m - first_m, 8), in_g = t - group * per_group;
+    tm = first_m + in_g % gm;
+    tn = in_g / gm;
+  }
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 16 * MI, wn0 = (wave & 1) * 32;
+  const int fr = lane & 15, fg = lane >> 4;
+
+  // Byte offset of chunk ch of row r (swizzled).
+  auto swz = [](int r, int ch) {
+    if constexpr (CH == 16) return r * ROWB + ((ch ^ ((r >> 2) & 3)) * CH);
+    else return r * ROWB + ((ch ^ ((r >> 3) & 3)) * CH);
+  };
+
+  // Global -> LDS staging.  Piece v = tid + i NT of a k-step covers 16 bytes
+  // of row r of slice s.  With PPR pieces per row and NT a multiple of PPR
+  // and of 16 rows, the per-lane part of every address is the same for all
+  // i (row tid / PPR, piece tid % PPR) and the rest is wave-uniform.
+  constexpr int PPR = ROWB / 16;                 // pieces per row: 4 or 2
+  constexpr int RPP = NT / PPR;                  // rows covered by one pass i
+  static_assert(RPP % 16 == 0, "swizzle needs whole 16-row groups per pass");
+  static_assert((RPP <= BM ? BM % RPP : RPP % BM) == 0 && (RPP <= BN ? BN % RPP : RPP % BN) == 0, "pass shape");
+  const int lr = tid / PPR, lp = tid % PPR;
+  // Lane part of the global offset for a tile of R rows (a pass may span
+  // several slices when it covers more rows than the tile has).
+  auto g_lane = [&](int R, int64_t slice_stride) -> int64_t {
+    return ((int64_t)(lr / R) * slice_stride + (int64_t)(lr % R) * g.kp) * ES + lp * 16;
+  };
+  const int64_t ga_lane = g_lane(BM, g.slice_stride_a);
+  const int64_t gb_lane = g_lane(BN, g.slice_stride_b);
+  // LDS position of (linear row lr, piece lp); the swizzle depends only on
+  // row bits 2..4, which whole-pass and whole-slice offsets leave unchanged.
+  const int l_lane_a = [&] {
+    if constexpr (CH == 16) return lr * ROWB + ((lp ^ ((lr >> 2) & 3)) * CH);
+    else return lr * ROWB + (((2 * lp) ^ ((lr >> 3) & 3)) * CH);
+  }();
+  const int l_lane_a2 = [&] {  // second 8-byte half (FP8 only)
+    if constexpr (CH == 16) return 0;
+    else return lr * ROWB + (((2 * lp + 1) ^ ((lr >> 3) & 3)) * CH);
+  }();
+  const unsigned char* ga = static_cast<const unsigned char*>(g.a) + m0 * g.kp * ES;
+  const unsigned char* gb = static_cast<const unsigned char*>(g.b) + n0 * g.kp * ES;
+  i4v ra[A_LD], rb[B_LD];
+  // Pass i of a tile of R rows starts at slice s, row r0.
+  auto pass_of = [&](int i, int R, int& s, int& r0) {
+    const int row_lin = i * RPP;
+    s = row_lin / R;
+    r0 = row_lin % R;
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      if (i * NT + tid < A_LD_TOTAL) {
+        int s, r0;
+        pass_of(i, BM, s, r0);
+        const unsigned char* base = ga + (s * g.slice_stride_a + (int64_t)r0 * g.kp + k0) * ES;
+        ra[i] = *reinterpret_cast<const i4v*>(base + ga_lane);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      if (i * NT + tid < B_LD_TOTAL) {
+        int s, r0;
+        pass_of(i, BN, s, r0);
+        const unsigned char* base = gb + (s * g.slice_stride_b + (int64_t)r0 * g.kp + k0) * ES;
+        rb[i] = *reinterpret_cast<const i4v*>(base + gb_lane);
+      }
+    }
+  };
+  auto put = [&](unsigned char* base, i4v x) {
+    if constexpr (CH == 16) {
+      *reinterpret_cast<i4v*>(base + l_lane_a) = x;
+    } else {
+      *reinterpret_cast<i2v*>(base + l_lane_a) = i2v{x[0], x[1]};
+      *reinterpret_cast<i2v*>(base + l_lane_a2) = i2v{x[2], x[3]};
+    }
+  };
+  auto lstore = [&](int st) {
+    unsigned char* base = lds + st * STAGE;
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      if (i * NT + tid < A_LD_TOTAL) {
+        int s, r0;
+        pass_of(i, BM, s, r0);
+        put(base + s * BM * ROWB + r0 * ROWB, ra[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      if (i * NT + tid < B_LD_TOTAL) {
+        int s, r0;
+        pass_of(i, BN, s, r0);
+        put(base + A_BYTES + s * BN * ROWB + r0 * ROWB, rb[i]);
+      }
+    }
+  };
+
+  d4s acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = d4s{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nk = g.kp / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int st = NSTAGE == 2 ? (int)(kt & 1) : 0;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+    const unsigned char* base = lds + st * STAGE;
+    frag_t fa[S][MI];
+    frag_t fbc[CACHE_B ? S : 1][NI];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+        fa[s][i] = *reinterpret_cast<const frag_t*>(base + s * BM * ROWB + swz(wm0 + i * 16 + fr, fg));
+      if constexpr (CACHE_B) {
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          fbc[s][j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + s * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
+      }
+    }
+#pragma unroll
+    for (int d = 2; d <= S + 1; ++d) {
+      // Keep each level's fragment reads and accumulators within the level:
+      // hoisting them across levels costs more registers than it hides.
+      __builtin_amdgcn_sched_barrier(0);
+      acc_t lv[MI][NI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) lv[i][j] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 1; s < d; ++s) {
+        const int t = d - s;
+        if (s > S || t > S) continue;
+        frag_t fb[NI];
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          if constexpr (CACHE_B)
+            fb[j] = fbc[t - 1][j];
+          else
+            fb[j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + (t - 1) * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j) lv[i][j] = Tr::mfma(fa[s - 1][i], fb[j], lv[i][j]);
+      }
+      const double sc = pow2neg(BETA * d);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] = __builtin_fma((double)lv[i][j][v], sc, acc[i][j][v]);
+    }
+    if (NSTAGE == 1) __syncthreads();
+    if (kt + 1 < nk) lstore(NSTAGE == 2 ? (st ^ 1) : 0);
+    __syncthreads();
+  }
+
+  // Epilogue: exponent scaling, then coef * T into every target block.
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = m0 + wm0 + i * 16 + 4 * fg + v;
+        const int64_t c = n0 + wn0 + j * 16 + fr;
+        if (r >= g.m || c >= g.n) continue;
+        const int ea = g.ea[r], eb = g.eb[c];
+        const double t = (ea == INT_MIN || eb == INT_MIN) ? 0.0 : ldexp(acc[i][j][v], ea + eb);
+        const int64_t off = r * g.ldc + c;
+        for (int q = 0; q < g.ntgt; ++q) {
+          double val = g.coef[q] * t;
+          if (g.mode[q] == TGT_ACCUM) val += g.c[q][off];
+          g.c[q][off] = val;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int ET, int S>
+static hipError_t launch_split_s(const SplitArgs& a, int* exps, void* out, hipStream_t st) {
+  const int64_t nexp = a.left ? a.rows_pad : a.cols_pad;
+  hipLaunchKernelGGL(fill_int, dim3((unsigned)((nexp + 255) / 256)), dim3(256), 0, st, exps, nexp, INT_MIN);
+  if (a.left) {
+    hipLaunchKernelGGL(split_exp_left, dim3((unsigned)a.rows, (unsigned)((a.cols + 2047) / 2048)), dim3(256), 0,
+                       st, a, exps);
+    hipLaunchKernelGGL((split_digits_left<ET, S>), dim3((unsigned)a.rows_pad, (unsigned)((a.kp + 2047) / 2048)),
+                       dim3(256), 0, st, a, exps, out);
+  } else {
+    hipLaunchKernelGGL(split_exp_right, dim3((unsigned)((a.cols + 63) / 64), (unsigned)((a.rows + 1023) / 1024)),
+                       dim3(256), 0, st, a, exps);
+    hipLaunchKernelGGL((split_digits_right<ET, S>), dim3((unsigned)(a.cols_pad / 64), (unsigned)(a.kp / 64)),
+                       dim3(256), 0, st, a, exps, out);
+  }
+  return hipGetLastError();
+}
+
+// Two block shapes, both with 32 x 32 wave tiles:
+//   variant 0: 8 waves (128 x 64 outputs), 2 waves/SIMD, B fragments read
+//              from LDS for every slice pair;
+//   variant 1: 4 waves (64 x 64 outputs), 1 wave/SIMD, every A and B
+//              fragment of the k-step cached in registers (half the LDS
+//              traffic, fewer waves to hide latency).
+// Default: variant 0 while it fits 256 registers without spilling.
+template <int ET, int S, int V>
+static hipError_t launch_slice_v(const SliceGemmArgs& g, hipStream_t st) {
+  typedef SliceTraits<ET> Tr;
+  constexpr int WM = V == 0 ? 4 : 2, CACHE_B = V == 0 ? 0 : 1, WPE = V == 0 ? 2 : 1;
+  constexpr int BM = 32 * WM;
+  constexpr int STAGE = S * (BM + 64) * Tr::KSTEP * Tr::ES;
+  constexpr int NSTAGE = 2 * STAGE <= 160 * 1024 ? 2 : 1;
+  static_assert(STAGE <= 160 * 1024, "slice tile does not fit LDS");
+  const int64_t tiles = ((g.m + BM - 1) / BM) * ((g.n + 63) / 64);
+  if (tiles <= 0) return hipSuccess;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((slice_gemm<ET, S, WM, 2, CACHE_B, NSTAGE, WPE>), dim3((unsigned)tiles), dim3(WM * 2 * 64),
+                     0, st, g);
+  return hipGetLastError();
+}
+
+int default_slice_variant(int et, int S) { return (et == 1 ? S <= 8 : S <= 6) ? 0 : 1; }
+
+template <int ET, int S>
+static hipError_t launch_slice_s(const SliceGemmArgs& g, int variant, hipStream_t st) {
+  if (variant < 0) variant = default_slice_variant(ET, S);
+  if (variant == 0) {
+    if constexpr (ET == 1 ? S <= 8 : S <= 6) return launch_slice_v<ET, S, 0>(g, st);
+    else return hipErrorInvalidValue;
+  }
+  return launch_slice_v<ET, S, 1>(g, st);
+}
+
+int slice_block_rows(int et, int S) {
+  (void)et;
+  (void)S;
+  return 128;  // digit rows are padded to 128, a multiple of both shapes
+}
+
+int slice_kstep(int et) { return et == 2 ? 64 : 32; }
+
+#define BQ_SPLIT_CASES(ET, X) \
+  X(ET, 1) X(ET, 2) X(ET, 3) X(ET, 4) X(ET, 5) X(ET, 6) X(ET, 7) X(ET, 8)
+#define BQ_SPLIT_CASES_MORE(X) \
+  X(1, 9) X(1, 10) X(1, 11) X(1, 12) X(1, 13) X(1, 14) X(2, 9)
+
+hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t st) {
+#define X(E, SS) \
+  if (et == E && S == SS) return launch_split_s<E, SS>(a, exps, out, st);
+  BQ_SPLIT_CASES(0, X)
+  BQ_SPLIT_CASES(1, X)
+  BQ_SPLIT_CASES(2, X)
+  BQ_SPLIT_CASES_MORE(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t st) {
+#define X(E, SS) \
+  if (et == E && S == SS) return launch_slice_s<E, SS>(g, variant, st);
+  BQ_SPLIT_CASES(0, X)
+  BQ_SPLIT_CASES(1, X)
+  BQ_SPLIT_CASES(2, X)
+  BQ_SPLIT_CASES_MORE(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int max_slices(int et) { return et == 0 ? 8 : (et == 1 ? 14 : 9); }
+
+}  // namespace bq

@@ -100,6 +100,12 @@ def test_unsupported_ops_and_precisions():
     assert check(A, Bm, C, opA=7) == INVALID
     assert check(A, Bm, C, prec=9) == INVALID
     assert check(A, Bm, C, slices=-1) == INVALID
+    # split forms: slice counts above the digit type's maximum are rejected
+    res_bf, _ = B.workspace_size(4, 4, 4, 0xFF, 0xFF, "split_bf16", 0)
+    assert check(A, Bm, C, prec=1, ws=4 * FAKE, ws_bytes=res_bf) == OK
+    assert check(A, Bm, C, prec=1, slices=9, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
+    assert check(A, Bm, C, prec=2, slices=15, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
+    assert check(A, Bm, C, prec=3, slices=10, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
 
 
 def test_alias_detection():
@@ -126,6 +132,11 @@ def test_workspace_sizes_and_errors():
     assert ws_need(m, n, k, 0x11, 0x11) == (0, 0)
     assert ws_need(m, n, k, 0x01, 0x01) == (0, 0)
     assert ws_need(m, n, 0) == (0, 0)
+    # split form: + digit buffers of one real product (rows padded to 128,
+    # columns to 64, k to 64; 2-byte BF16 digits, S = 7 by default)
+    r_bf, m_bf = B.workspace_size(m, n, k, 0xFF, 0xFF, "split_bf16", 0)
+    dig = lambda rows: (7 * rows * 64 * 2 + 255) // 256 * 256 + (rows * 4 + 255) // 256 * 256
+    assert r_bf == res + dig(128) + dig(64) and m_bf == mn + dig(128) + dig(64)
     A, Bm, C = mat(m, k, FAKE), mat(k, n, 2 * FAKE), mat(m, n, 3 * FAKE)
     assert check(A, Bm, C, ws=4 * FAKE, ws_bytes=mn - 1) == WORKSPACE
     assert check(A, Bm, C, ws=None, ws_bytes=0) == WORKSPACE

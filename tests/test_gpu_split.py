@@ -1,0 +1,117 @@
+"""Split-precision (Ozaki-style) path on the GPU, through the C-ABI.
+
+* Integer inputs whose digits fit the kept slices: bit-exact with the oracle.
+* Random inputs: equal to the CPU split model (tests/bilinear_model.py with
+  oracle/ozaki.py as the real GEMM: the same digits and pairs, exact digit
+  products) to 1e-14 relative, the two differing only in FP64 summation order.
+* At the default slice counts: relative Frobenius error <= 1e-12 against the
+  FP64 oracle (uniform and log-spread inputs, n = 256 and sampled n = 8192).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from bilinear_model import Counter, bilinear
+from oracle import ozaki
+from paper_2609_02081_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+PRECS = {"bf16": "split_bf16", "fp8": "split_fp8", "int8": "split_int8"}
+DEFAULT_S = {"bf16": 7, "fp8": 13, "int8": 8}
+
+
+@pytest.fixture(scope="module")
+def bq():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_02081_amd as bq
+
+    bq.lib()
+    return bq
+
+
+def run(bq, A, B, kind, S, **kw):
+    import torch
+
+    C = bq.bq_gemm(torch.from_numpy(A).to("cuda"), torch.from_numpy(B).to("cuda"), prec=PRECS[kind],
+                   slices=S, **kw)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,S", [("bf16", 4), ("fp8", 6), ("int8", 4)])
+def test_integer_bit_exact(bq, kind, S):
+    A, B = inputs.pair(96, 80, 72, "int", seed=12, bound=64)
+    print(f"split {kind} S={S} integer", flush=True)
+    assert np.array_equal(run(bq, A, B, kind, S), oracle.gemm(A, B))
+
+
+@pytest.mark.parametrize("variant", ["0", "1"])
+@pytest.mark.parametrize("kind,S", [("bf16", 3), ("bf16", 6), ("bf16", 8), ("fp8", 5), ("fp8", 9),
+                                    ("fp8", 13), ("int8", 4), ("int8", 7), ("int8", 9)])
+def test_matches_cpu_split_model(bq, kind, S, variant, monkeypatch):
+    """Both slice-GEMM block shapes (the 8-wave one exists up to S = 6, or
+    S = 8 for FP8) against the CPU split model; ragged shape."""
+    if variant == "0" and S > (8 if kind == "fp8" else 6):
+        pytest.skip("8-wave shape not built for this many slices")
+    monkeypatch.setenv("BQ_SLICE_VARIANT", variant)
+    A, B = inputs.pair(130, 100, 70, "uniform", seed=13)
+    print(f"split {kind} S={S} variant {variant} vs model", flush=True)
+    ref = bilinear(A, B, Counter(lambda x, y: ozaki.product(x, y, kind, S)))
+    got = run(bq, A, B, kind, S)
+    assert oracle.rel_frobenius(got, ref) <= 1e-14
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
+@pytest.mark.parametrize("dist", ["uniform", "logspread"])
+def test_default_slices_accuracy(bq, kind, dist):
+    A, B = inputs.pair(256, 256, 256, dist, seed=4)
+    err = oracle.rel_frobenius(run(bq, A, B, kind, 0), oracle.gemm(A, B))
+    print(f"split {kind} default S, {dist}: rel err {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("kind", ["bf16", "int8"])
+def test_conj_and_masks(bq, kind):
+    A, B = inputs.pair(90, 70, 60, "normal", seed=14)
+    got = run(bq, A, B, kind, 0, opA="C")
+    assert oracle.rel_frobenius(got, oracle.gemm(oracle.conj(A), B)) <= TOL
+    for name in ("real_quaternion", "complex", "real"):
+        mask = inputs.MASKS[name]
+        Am, Bm = inputs.pair(90, 70, 60, "normal", seed=15, mask_a=mask, mask_b=mask)
+        got = run(bq, Am, Bm, kind, 0, mask_a=mask, mask_b=mask)
+        assert oracle.rel_frobenius(got, oracle.gemm(Am, Bm)) <= TOL, name
+
+
+def _sample(n, r, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n - 1, size=r - 1, replace=False))
+    return np.append(idx, n - 1)
+
+
+@pytest.mark.parametrize("kind", ["bf16", "int8", "fp8"])
+@pytest.mark.parametrize("dist", ["uniform", "logspread"])
+def test_n8192_sampled(bq, kind, dist):
+    import torch
+
+    n, r = 8192, 48
+    rng = np.random.default_rng(4)
+    print(f"split n=8192 {kind} {dist}: inputs", flush=True)
+    if dist == "uniform":
+        A = inputs.device_uniform(n, n, 41, "cuda")
+        B = inputs.device_uniform(n, n, 42, "cuda")
+    else:
+        A = torch.from_numpy(inputs.blocks(rng, n, n, "logspread")).to("cuda")
+        B = torch.from_numpy(inputs.blocks(rng, n, n, "logspread")).to("cuda")
+    C = bq.bq_gemm(A, B, prec=PRECS[kind])
+    torch.cuda.synchronize()
+    rows, cols = _sample(n, r, 51), _sample(n, r, 52)
+    ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+    As, Bs = A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy()
+    Cs = C[:, ri][:, :, ci].cpu().numpy()
+    err = oracle.rel_frobenius(Cs, oracle.gemm(As, Bs))
+    print(f"split n=8192 {kind} {dist}: sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL

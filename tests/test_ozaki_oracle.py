@@ -1,0 +1,87 @@
+"""Pins for the split-form oracle (oracle/ozaki.py): exact reconstruction,
+digit bounds, exact integer products, and convergence to the FP64 product
+at the rate one digit (beta bits) per slice predicts."""
+import numpy as np
+import pytest
+
+from oracle import ozaki
+from paper_2609_02081_amd import inputs
+
+KINDS = [("bf16", 8), ("fp8", 14), ("int8", 9)]
+
+
+@pytest.mark.parametrize("kind,S", KINDS)
+@pytest.mark.parametrize("dist", ["uniform", "logspread", "normal"])
+def test_reconstruction(kind, S, dist):
+    """x = 2^e (sum_s q_s 2^-bs + rem) exactly, |rem| <= 2^(-bS-1); numpy's
+    uniform draws are multiples of 2^-52, so S * beta >= 53 digits hold them
+    with no remainder at all."""
+    beta = ozaki.BETA[kind]
+    rng = np.random.default_rng(5)
+    X = inputs.blocks(rng, 20, 33, dist)[0]
+    for axis in (1, 0):
+        Q, e, rem = ozaki.digits(X, beta, S, axis)
+        ee = e[:, None] if axis == 1 else e[None, :]
+        rec = sum(np.ldexp(Q[s].astype(np.float64), -beta * (s + 1)) for s in range(S))
+        assert np.array_equal(np.ldexp(rec + rem, ee), X)
+        assert np.max(np.abs(rem)) <= 2.0 ** (-beta * S - 1)
+        if dist == "uniform":
+            assert np.array_equal(np.ldexp(rec, ee), X)
+
+
+@pytest.mark.parametrize("kind,S", [("bf16", 6), ("fp8", 11), ("int8", 7)])
+def test_digit_bounds(kind, S):
+    beta = ozaki.BETA[kind]
+    rng = np.random.default_rng(6)
+    X = inputs.blocks(rng, 40, 50, "logspread")[0]
+    Q, e, rem = ozaki.digits(X, beta, S, 1)
+    assert np.max(np.abs(Q[0])) <= 2 ** beta
+    for s in range(1, S):
+        assert np.max(np.abs(Q[s])) <= 2 ** (beta - 1)
+    assert np.max(np.abs(rem)) <= 2.0 ** (-beta * S - 1)
+    # the digit types hold these integers exactly
+    lim = {"bf16": 256, "fp8": 16, "int8": 127}[kind]
+    assert max(np.max(np.abs(q)) for q in Q) <= lim
+
+
+@pytest.mark.parametrize("kind,S", [("bf16", 3), ("fp8", 5), ("int8", 3)])
+def test_integer_products_exact(kind, S):
+    """Integers of at most 10 bits need 2 (bf16, int8) or 3 (fp8) digits;
+    with those pairs kept the split product is exact."""
+    rng = np.random.default_rng(7)
+    X = rng.integers(-512, 513, size=(30, 70)).astype(np.float64)
+    Y = rng.integers(-512, 513, size=(70, 20)).astype(np.float64)
+    ref = (X.astype(np.int64) @ Y.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(ozaki.product(X, Y, kind, S), ref)
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
+def test_convergence_rate(kind):
+    """The error falls by about 2^-beta per added slice until FP64 rounding."""
+    beta = ozaki.BETA[kind]
+    rng = np.random.default_rng(8)
+    X = rng.uniform(-1, 1, (48, 96))
+    Y = rng.uniform(-1, 1, (96, 40))
+    ref = X @ Y
+    errs = []
+    for S in range(2, 6):
+        T = ozaki.product(X, Y, kind, S)
+        errs.append(np.linalg.norm(T - ref) / np.linalg.norm(ref))
+    for a, b in zip(errs, errs[1:]):
+        assert b < a * 2.0 ** (-beta + 2), errs
+
+
+@pytest.mark.parametrize("kind,S", KINDS)
+def test_full_slices_match_fp64(kind, S):
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((40, 64))
+    Y = rng.standard_normal((64, 30))
+    ref = X @ Y
+    T = ozaki.product(X, Y, kind, S)
+    assert np.linalg.norm(T - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+def test_zero_rows_and_columns():
+    X = np.zeros((5, 7)); X[1] = np.arange(7) + 1.0
+    Y = np.zeros((7, 4)); Y[:, 2] = 1.0
+    assert np.array_equal(ozaki.product(X, Y, "bf16", 4), X @ Y)
