@@ -144,6 +144,46 @@ bq_status_t bq_rq_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B
  * 24 full, 8 real quaternion, 3 complex, 1 real).  Host only. */
 int bq_plan_real_gemms(unsigned maskA, unsigned maskB);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent products C_p = op(A_p) op(B_p) of
+ * different sizes in one plan.  For FP64 the plan runs as one graph: a
+ * pre-combination launch for every problem, then one persistent launch whose
+ * blocks take (problem, 64 x 64 tile) work items, largest problems first,
+ * and run the problem's eight complex products on that tile in turn; the
+ * split forms replay every problem's split-precision sequence in one graph.
+ *
+ * Pointers in the problems are baked into the plan: A, B, C of every problem
+ * must stay valid (and C must not overlap any A, B or other C) until the
+ * plan is destroyed.  FP64 plans need full biquaternions (all 16 input
+ * components present) and op N or C; others return BQ_ERR_UNSUPPORTED.
+ * Plan creation allocates the plan's device tables (hipMalloc, once);
+ * launching allocates nothing.  A plan is bound to the workspace pointer of
+ * its first launch: a later launch with another pointer re-records the graph.
+ * Calls on one plan must not overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  bq_op_t opA, opB;
+  bq_matrix_t A, B, C;
+} bq_problem_t;
+
+typedef struct bq_grouped_plan_s* bq_grouped_plan_t;
+
+bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t* problems, bq_prec_t prec,
+                                   int slices, bq_grouped_plan_t* plan);
+/* Device workspace one launch needs (bytes). */
+bq_status_t bq_grouped_plan_workspace_size(bq_grouped_plan_t plan, size_t* bytes);
+/* Autotuner: times every candidate tile configuration and work schedule of
+ * the FP64 plan on the given workspace and stream (synchronising it), keeps
+ * the fastest, and records it in the cache file named by BQ_TUNE_CACHE (if
+ * set) under a key of device architecture, CU count, precision and problem
+ * sizes; a later plan with the same key reads it back at creation.  For the
+ * split forms it returns BQ_OK without changes. */
+bq_status_t bq_grouped_plan_autotune(bq_grouped_plan_t plan, void* ws, size_t ws_bytes, bq_stream_t stream);
+bq_status_t bq_grouped_plan_launch(bq_grouped_plan_t plan, void* ws, size_t ws_bytes, bq_stream_t stream);
+/* Chosen tile configuration, schedule (1 = dynamic counter) and work items. */
+bq_status_t bq_grouped_plan_info(bq_grouped_plan_t plan, int* tile_config, int* dynamic_schedule, int* work_items);
+bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan);
+
 /* Launch tracing (measurement support, not part of the product semantics).
  * While enabled, every kernel the handle enqueues is bracketed by a pair of
  * HIP events recorded on the same stream.  bq_trace_read waits for the
@@ -159,8 +199,10 @@ typedef enum {
   BQ_KERNEL_COMBINE = 10,   /* Hadamard pre-combination              */
   BQ_KERNEL_FILL = 11,      /* zero fill of a structurally zero block */
   BQ_KERNEL_SPLIT = 12,     /* exponents + digit slices of one operand */
-  BQ_KERNEL_SLICE_GEMM = 13 /* one real product from digit slices;
+  BQ_KERNEL_SLICE_GEMM = 13, /* one real product from digit slices;
                                flops = pairs * 2 m n k, config = slices */
+  BQ_KERNEL_GROUPED = 14     /* one launch of a batched plan (whole graph);
+                               flops = executed real-GEMM flops of all problems */
 } bq_kernel_t;
 
 typedef struct {

@@ -25,6 +25,10 @@ class BqMatrix(ctypes.Structure):
                 ("cols", ctypes.c_int64), ("ld", ctypes.c_int64)]
 
 
+class BqProblem(ctypes.Structure):
+    _fields_ = [("opA", ctypes.c_int), ("opB", ctypes.c_int), ("A", BqMatrix), ("B", BqMatrix), ("C", BqMatrix)]
+
+
 class BqTraceRecord(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("config", ctypes.c_int), ("m", ctypes.c_int64),
                 ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("ms", ctypes.c_double),
@@ -32,7 +36,7 @@ class BqTraceRecord(ctypes.Structure):
 
 
 KERNEL_NAMES = {0: "gemm_gauss", 1: "gemm_rc", 2: "gemm_cr", 3: "gemm_rr", 10: "combine", 11: "fill",
-                12: "split", 13: "slice_gemm"}
+                12: "split", 13: "slice_gemm", 14: "grouped"}
 
 
 class BqError(RuntimeError):
@@ -64,6 +68,15 @@ _SIGS = [
     ("bq_rq_gemm", ctypes.c_int,
      [ctypes.c_void_p, _M, _M, _M, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("bq_plan_real_gemms", ctypes.c_int, [ctypes.c_uint, ctypes.c_uint]),
+    ("bq_grouped_plan_create", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(BqProblem), ctypes.c_int, ctypes.c_int,
+      ctypes.POINTER(ctypes.c_void_p)]),
+    ("bq_grouped_plan_workspace_size", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    ("bq_grouped_plan_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("bq_grouped_plan_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("bq_grouped_plan_info", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    ("bq_grouped_plan_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("bq_trace_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bq_trace_read", ctypes.c_int,
      [ctypes.c_void_p, ctypes.POINTER(BqTraceRecord), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -236,3 +249,63 @@ def trace_read(device: int = 0, cap: int = 4096) -> list[dict]:
                         "m": r.m, "n": r.n, "k": r.k, "ms": r.ms, "flops": r.flops, "bytes": r.bytes})
         if cnt.value < cap:
             return out
+
+
+class GroupedPlan:
+    """Batched plan over (A, B, C) triples of (8, rows, cols) device tensors.
+
+    The tensors are referenced by the plan and must stay alive (this object
+    keeps them) until close().  Workspace comes from torch unless given."""
+
+    def __init__(self, problems, prec="fp64", slices=0, opA="N", opB="N", device=0):
+        self._keep = []
+        arr = (BqProblem * max(1, len(problems)))()
+        for i, (A, B, C) in enumerate(problems):
+            arr[i].opA, arr[i].opB = OPS[opA], OPS[opB]
+            arr[i].A, arr[i].B, arr[i].C = matrix(A), matrix(B), matrix(C)
+            self._keep.append((A, B, C))
+        self.device = device
+        self._plan = ctypes.c_void_p()
+        check(lib().bq_grouped_plan_create(handle(device), len(problems), arr, PRECS[prec], slices,
+                                           ctypes.byref(self._plan)))
+        self._ws = None
+
+    def workspace_size(self) -> int:
+        b = ctypes.c_size_t()
+        check(lib().bq_grouped_plan_workspace_size(self._plan, ctypes.byref(b)))
+        return b.value
+
+    def workspace(self):
+        import torch
+
+        if self._ws is None:
+            self._ws = torch.empty(max(1, self.workspace_size()), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def autotune(self, workspace=None, stream=None):
+        ws = self.workspace() if workspace is None else workspace
+        check(lib().bq_grouped_plan_autotune(self._plan, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                             _stream(stream)))
+
+    def launch(self, workspace=None, stream=None):
+        ws = self.workspace() if workspace is None else workspace
+        check(lib().bq_grouped_plan_launch(self._plan, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                           _stream(stream)))
+
+    def info(self) -> dict:
+        c, d, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().bq_grouped_plan_info(self._plan, ctypes.byref(c), ctypes.byref(d), ctypes.byref(n)))
+        return {"tile_config": c.value, "dynamic": d.value, "work_items": n.value}
+
+    def close(self):
+        if self._plan:
+            lib().bq_grouped_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+        self._keep = []
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

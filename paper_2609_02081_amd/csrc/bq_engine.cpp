@@ -4,6 +4,8 @@
 // GEMMs for the active components), workspace carving and kernel launches.
 #include <algorithm>
 #include <cstdint>
+#include <fstream>
+#include <sstream>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
@@ -284,7 +286,8 @@ bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) !=
 // call writes (all of them must be non-null).
 bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
                      const bq_matrix_t* C, bq_prec_t prec, int slices, const void* ws,
-                     size_t ws_bytes, unsigned out_mask, Plan* plan_out, bool* streamed, Prec* prec_out) {
+                     size_t ws_bytes, unsigned out_mask, Plan* plan_out, bool* streamed, Prec* prec_out,
+                     bool check_ws = true) {
   if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
   auto op_ok = [](bq_op_t o) { return o == BQ_OP_N || o == BQ_OP_T || o == BQ_OP_C || o == BQ_OP_H; };
   if (!op_ok(opA) || !op_ok(opB)) return fail(BQ_ERR_INVALID_VALUE, "op must be N, T, C or H");
@@ -315,17 +318,17 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
         return fail(BQ_ERR_INVALID_VALUE, "output component " + std::to_string(c) + " is null");
   if (opA == BQ_OP_T || opA == BQ_OP_H || opB == BQ_OP_T || opB == BQ_OP_H)
     return fail(BQ_ERR_UNSUPPORTED, "op T and H are not implemented in this build");
-  if (ws_bytes > 0 && !ws) return fail(BQ_ERR_INVALID_VALUE, "ws is null but ws_bytes > 0");
+  if (check_ws && ws_bytes > 0 && !ws) return fail(BQ_ERR_INVALID_VALUE, "ws is null but ws_bytes > 0");
 
   const int64_t m = A->rows, n = B->cols, k = A->cols;
   Plan plan = make_plan(problem_of(opA, opB, A, B));
   size_t res = 0, mn = 0;
   workspace_need(plan, pr, m, n, k, &res, &mn);
-  if (ws_bytes < mn)
+  if (check_ws && ws_bytes < mn)
     return fail(BQ_ERR_WORKSPACE, "workspace " + std::to_string(ws_bytes) + " B < minimum " + std::to_string(mn) + " B");
   const char* fs = std::getenv("BQ_FORCE_STREAMED");
   const bool force_stream = fs && fs[0] == '1';
-  const bool use_stream = (ws_bytes < res) || (force_stream && mn < res);
+  const bool use_stream = check_ws && ((ws_bytes < res) || (force_stream && mn < res));
 
   // Aliasing: output blocks against inputs, workspace and each other.
   if (m > 0 && n > 0) {
@@ -340,7 +343,7 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
       }
     }
     const size_t used_ws = use_stream ? mn : res;
-    if (ws && used_ws > 0) {
+    if (check_ws && ws && used_ws > 0) {
       const uintptr_t lo = reinterpret_cast<uintptr_t>(ws);
       ins.push_back({lo, lo + used_ws});
     }
@@ -826,6 +829,455 @@ bq_status_t bq_rq_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B
   bq_matrix_t a = restrict_to(A, BQ_MASK_REAL_QUATERNION), b = restrict_to(B, BQ_MASK_REAL_QUATERNION),
               c = restrict_to(C, BQ_MASK_REAL_QUATERNION);
   return run(h, BQ_OP_N, BQ_OP_N, &a, &b, &c, BQ_PREC_FP64, 0, ws, ws_bytes, BQ_MASK_REAL_QUATERNION, stream);
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form (grouped plans)
+// ===========================================================================
+struct bq_grouped_plan_s {
+  bq_handle_t h = nullptr;
+  int count = 0;
+  Prec pr;
+  std::vector<bq_problem_t> probs;
+  std::vector<Plan> plans;
+  std::vector<size_t> ws_off;  // FP64: each problem's pre-combination buffers
+  size_t ws_bytes = 0;
+  bq::GemmArgs* d_prods = nullptr;
+  bq::GroupedItem* d_items = nullptr;
+  int* d_counter = nullptr;
+  bq::CombineArgs* d_comb = nullptr;
+  int64_t* d_prefix = nullptr;
+  int nitems = 0;
+  int ncomb = 0;
+  int64_t total_rows = 0;
+  std::vector<int> order;  // problems, largest work first
+  int cfg = 0, dyn = 1;
+  int blocks = 0;
+  double flops = 0.0;
+  void* bound_ws = nullptr;
+  bool bound = false;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string tune_key;
+};
+
+namespace {
+
+constexpr int kGroupedTile = 64;  // both grouped tile configurations are 64 x 64
+
+void grouped_release_graph(bq_grouped_plan_t p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  p->exec = nullptr;
+  p->bound = false;
+}
+
+std::string tune_cache_path() {
+  const char* e = std::getenv("BQ_TUNE_CACHE");
+  return e ? std::string(e) : std::string();
+}
+
+bool tune_cache_lookup(const std::string& key, int* cfg, int* dyn) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream ss(line);
+    std::string k;
+    int c = -1, d = -1;
+    if (ss >> k >> c >> d && k == key && (c == 0 || c == 6) && (d == 0 || d == 1)) {
+      *cfg = c;
+      *dyn = d;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  return found;
+}
+
+void tune_cache_store(const std::string& key, int cfg, int dyn) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << cfg << " " << dyn << "\n";
+}
+
+// Host tables of an FP64 plan for workspace ws, copied to the device, then
+// the graph [grouped pre-combination -> persistent grouped GEMM] recorded.
+bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
+  grouped_release_graph(p);
+  const bool trace = p->h->trace;
+  p->h->trace = false;  // no trace events inside the recorded graph
+  struct Restore {
+    bq_handle_t h;
+    bool t;
+    ~Restore() { h->trace = t; }
+  } restore{p->h, trace};
+  hipError_t e = hipSuccess;
+  bq_status_t st = BQ_OK;
+  if (p->pr.et >= 0) {
+    e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    // Split forms: every problem's split-precision sequence, one after another
+    // on the capture stream, sharing the workspace.
+    for (int i = 0; i < p->count && st == BQ_OK; ++i) {
+      bq_problem_t& q = p->probs[p->order[i]];
+      st = execute(p->h, p->plans[p->order[i]], p->pr, &q.A, &q.B, &q.C, 0xFFu, ws, false, p->cap);
+    }
+  } else {
+    std::vector<bq::CombineArgs> comb;
+    std::vector<int64_t> prefix;
+    std::vector<bq::GemmArgs> prods(size_t(p->count) * 8);
+    int64_t rows = 0;
+    for (int pi = 0; pi < p->count; ++pi) {
+      const bq_problem_t& q = p->probs[pi];
+      const Plan& pl = p->plans[pi];
+      const int64_t m = q.A.rows, n = q.B.cols, k = q.A.cols;
+      char* wp = static_cast<char*>(ws) + p->ws_off[pi];
+      const size_t a1 = align256(size_t(m) * size_t(k) * 8), b1 = align256(size_t(k) * size_t(n) * 8);
+      double *cAr[4], *cAi[4], *cBr[4], *cBi[4];
+      for (int c = 0; c < 4; ++c) {
+        cAr[c] = reinterpret_cast<double*>(wp); wp += a1;
+        cAi[c] = reinterpret_cast<double*>(wp); wp += a1;
+        cBr[c] = reinterpret_cast<double*>(wp); wp += b1;
+        cBi[c] = reinterpret_cast<double*>(wp); wp += b1;
+      }
+      for (int side = 0; side < 2; ++side) {
+        bq::CombineArgs ca{};
+        const bq_matrix_t& X = side == 0 ? q.A : q.B;
+        for (int c = 0; c < 8; ++c) ca.src[c] = X.comp[c];
+        ca.lds = X.ld;
+        ca.rows = side == 0 ? m : k;
+        ca.cols = side == 0 ? k : n;
+        ca.ldd = ca.cols;
+        ca.nq = 4;
+        for (int j = 0; j < 4; ++j) {
+          ca.dst_r[j] = side == 0 ? cAr[j] : cBr[j];
+          ca.dst_i[j] = side == 0 ? cAi[j] : cBi[j];
+          for (int u = 0; u < 4; ++u) ca.w[j][u] = side == 0 ? pl.wA[j][u] : pl.wB[j][u];
+        }
+        prefix.push_back(rows);
+        rows += ca.rows;
+        comb.push_back(ca);
+      }
+      bool touched[8] = {};
+      int qi = 0;
+      for (const Prod& pd : pl.prods) {
+        Operand L = pd.L, R = pd.R;
+        if (L.combo >= 0) {
+          L.r = cAr[L.combo]; L.i = cAi[L.combo]; L.ld = k;
+          R.r = cBr[R.combo]; R.i = cBi[R.combo]; R.ld = n;
+        }
+        bq::GemmArgs g{};
+        g.lr = L.r; g.li = L.i; g.lda = L.ld;
+        g.rr = R.r; g.ri = R.i; g.ldb = R.ld;
+        g.m = m; g.n = n; g.k = k;
+        g.sL = L.s; g.sR = R.s;
+        g.ldc = q.C.ld;
+        g.xcd_remap = 0;
+        g.group_m = 1;
+        auto al16 = [](const double* x) { return (reinterpret_cast<uintptr_t>(x) & 15u) == 0; };
+        g.vec = (g.lda % 2 == 0) && (g.ldb % 2 == 0) && al16(g.lr) && al16(g.li) && al16(g.rr) && al16(g.ri);
+        for (const Tgt& t : pd.tgts) {
+          bq::Target T{};
+          T.ar = t.coef.re;
+          T.ai = t.coef.im;
+          T.cr = q.C.comp[t.w];
+          T.ci = q.C.comp[t.w + 4];
+          T.mode_r = touched[t.w] ? bq::TGT_ACCUM : bq::TGT_WRITE;
+          T.mode_i = touched[t.w + 4] ? bq::TGT_ACCUM : bq::TGT_WRITE;
+          touched[t.w] = touched[t.w + 4] = true;
+          g.tgt[g.ntgt++] = T;
+        }
+        prods[size_t(pi) * 8 + qi++] = g;
+      }
+    }
+    // Tables go to the device before recording (a synchronous copy may not
+    // run while this thread records a graph).
+    e = hipMemcpy(p->d_prods, prods.data(), prods.size() * sizeof(bq::GemmArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_comb, comb.data(), comb.size() * sizeof(bq::CombineArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_prefix, prefix.data(), prefix.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "grouped table upload");
+    e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    e = bq::launch_grouped_combine(p->d_comb, p->d_prefix, p->ncomb, rows, p->cap);
+    if (e == hipSuccess) e = bq::launch_grouped(p->cfg, p->dyn, p->d_prods, p->d_items, p->nitems, p->d_counter,
+                                                p->blocks, p->cap);
+    if (e != hipSuccess) st = hip_fail(e, "grouped launch");
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(p->cap, &graph);
+  if (st != BQ_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+  e2 = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate");
+  p->bound_ws = ws;
+  p->bound = true;
+  return BQ_OK;
+}
+
+bq_status_t grouped_check_ws(bq_grouped_plan_t p, void* ws, size_t ws_bytes) {
+  if (ws_bytes < p->ws_bytes)
+    return fail(BQ_ERR_WORKSPACE, "workspace " + std::to_string(ws_bytes) + " B < " + std::to_string(p->ws_bytes) + " B");
+  if (p->ws_bytes > 0 && !ws) return fail(BQ_ERR_INVALID_VALUE, "ws is null");
+  // the workspace must not overlap any problem's operands
+  if (ws && p->ws_bytes > 0) {
+    const Range w{reinterpret_cast<uintptr_t>(ws), reinterpret_cast<uintptr_t>(ws) + p->ws_bytes};
+    for (const bq_problem_t& q : p->probs) {
+      const bq_matrix_t* M[3] = {&q.A, &q.B, &q.C};
+      for (const bq_matrix_t* X : M)
+        if (X->rows > 0 && X->cols > 0)
+          for (int c = 0; c < 8; ++c)
+            if (X->comp[c] && overlaps(w, block_range(X->comp[c], X->rows, X->cols, X->ld)))
+              return fail(BQ_ERR_ALIAS, "workspace overlaps a problem's matrix");
+    }
+  }
+  return BQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t* problems, bq_prec_t prec, int slices,
+                                   bq_grouped_plan_t* plan) {
+  if (!plan) return fail(BQ_ERR_INVALID_VALUE, "plan is null");
+  *plan = nullptr;
+  if (!h) return fail(BQ_ERR_INVALID_VALUE, "handle is null");
+  if (count < 0 || (count > 0 && !problems)) return fail(BQ_ERR_INVALID_VALUE, "bad problem list");
+  Prec pr;
+  if (bq_status_t ps = prec_of(prec, slices, &pr); ps != BQ_OK) return ps;
+  std::vector<Plan> plans(count);
+  std::vector<size_t> offs(count, 0);
+  size_t total_ws = 0;
+  std::vector<std::pair<Range, int>> outs, ins;  // (range, problem)
+  double flops = 0.0;
+  for (int i = 0; i < count; ++i) {
+    const bq_problem_t& q = problems[i];
+    Plan pl;
+    bool streamed = false;
+    Prec dummy;
+    bq_status_t st = validate(q.opA, q.opB, &q.A, &q.B, &q.C, prec, slices, nullptr, 0, 0xFFu, &pl, &streamed,
+                              &dummy, false);
+    if (st != BQ_OK) return fail(st, "problem " + std::to_string(i) + ": " + g_detail);
+    const int64_t m = q.A.rows, n = q.B.cols, k = q.A.cols;
+    if (pr.et < 0) {
+      for (int c = 0; c < 8; ++c)
+        if (!q.A.comp[c] || !q.B.comp[c])
+          return fail(BQ_ERR_UNSUPPORTED, "problem " + std::to_string(i) +
+                                              ": FP64 batched plans need all 16 input components");
+      if (m == 0 || n == 0 || k == 0)
+        return fail(BQ_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": FP64 batched plans need m, n, k > 0");
+    }
+    size_t res = 0, mn = 0;
+    workspace_need(pl, pr, m, n, k, &res, &mn);
+    if (pr.et < 0) {
+      offs[i] = total_ws;
+      total_ws += res;
+    } else {
+      total_ws = std::max(total_ws, res);
+    }
+    flops += double(pl.real_gemms) * 2.0 * double(m) * double(n) * double(k);
+    plans[i] = pl;
+    if (m > 0 && n > 0) {
+      for (int c = 0; c < 8; ++c) {
+        if (q.C.comp[c]) outs.push_back({block_range(q.C.comp[c], m, n, q.C.ld), i});
+        if (k > 0) {
+          if (q.A.comp[c]) ins.push_back({block_range(q.A.comp[c], m, k, q.A.ld), i});
+          if (q.B.comp[c]) ins.push_back({block_range(q.B.comp[c], k, n, q.B.ld), i});
+        }
+      }
+    }
+  }
+  // Problems run concurrently: no C may overlap any other matrix of any problem.
+  {
+    std::vector<std::pair<Range, int>> all;  // second: -1 input, else output index
+    for (auto& r : ins) all.push_back({r.first, -1});
+    for (size_t j = 0; j < outs.size(); ++j) all.push_back({outs[j].first, int(j)});
+    std::sort(all.begin(), all.end(), [](const auto& a, const auto& b) { return a.first.lo < b.first.lo; });
+    uintptr_t reach = 0;
+    bool reach_out = false;
+    for (size_t j = 0; j < all.size(); ++j) {
+      const bool is_out = all[j].second >= 0;
+      if (j > 0 && all[j].first.lo < reach && (is_out || reach_out))
+        return fail(BQ_ERR_ALIAS, "a C block overlaps another matrix of the batch");
+      if (all[j].first.hi > reach) {
+        reach = all[j].first.hi;
+        reach_out = is_out;
+      } else if (is_out) {
+        reach_out = true;
+      }
+    }
+  }
+  bq_status_t st = check_handle(h);
+  if (st != BQ_OK) return st;
+
+  auto* p = new bq_grouped_plan_s;
+  p->h = h;
+  p->count = count;
+  p->pr = pr;
+  p->probs.assign(problems, problems + count);
+  p->plans = std::move(plans);
+  p->ws_off = std::move(offs);
+  p->ws_bytes = total_ws;
+  p->flops = flops;
+  p->order.resize(count);
+  for (int i = 0; i < count; ++i) p->order[i] = i;
+  auto work = [&](int i) {
+    const bq_problem_t& q = p->probs[i];
+    return double(q.A.rows) * double(q.B.cols) * double(q.A.cols);
+  };
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) { return work(a) > work(b); });
+  p->blocks = 2 * std::max(1, h->cu_count);
+
+  std::ostringstream key;
+  key << h->arch << ":" << h->cu_count << ":" << pr.et << ":" << pr.S << ":";
+  uint64_t hash = 1469598103934665603ull;
+  for (int i : p->order) {
+    const bq_problem_t& q = p->probs[i];
+    const int64_t d[3] = {q.A.rows, q.B.cols, q.A.cols};
+    for (int64_t x : d) {
+      hash ^= uint64_t(x);
+      hash *= 1099511628211ull;
+    }
+  }
+  key << std::hex << hash;
+  p->tune_key = key.str();
+  (void)tune_cache_lookup(p->tune_key, &p->cfg, &p->dyn);
+
+  hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess && pr.et < 0 && count > 0) {
+    std::vector<bq::GroupedItem> items;
+    for (int i : p->order) {
+      const bq_problem_t& q = p->probs[i];
+      const int tm = int((q.A.rows + kGroupedTile - 1) / kGroupedTile);
+      const int tn = int((q.B.cols + kGroupedTile - 1) / kGroupedTile);
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b) items.push_back({i * 8, int(p->plans[i].prods.size()), a, b});
+    }
+    p->nitems = int(items.size());
+    p->ncomb = 2 * count;
+    e = hipMalloc(&p->d_prods, sizeof(bq::GemmArgs) * size_t(count) * 8);
+    if (e == hipSuccess) e = hipMalloc(&p->d_items, sizeof(bq::GroupedItem) * items.size());
+    if (e == hipSuccess) e = hipMalloc(&p->d_counter, 256);
+    if (e == hipSuccess) e = hipMalloc(&p->d_comb, sizeof(bq::CombineArgs) * size_t(p->ncomb));
+    if (e == hipSuccess) e = hipMalloc(&p->d_prefix, sizeof(int64_t) * size_t(p->ncomb));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_items, items.data(), sizeof(bq::GroupedItem) * items.size(), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    bq_grouped_plan_destroy(p);
+    return hip_fail(e, "grouped plan setup");
+  }
+  *plan = p;
+  return BQ_OK;
+}
+
+bq_status_t bq_grouped_plan_workspace_size(bq_grouped_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(BQ_ERR_INVALID_VALUE, "null argument");
+  *bytes = plan->ws_bytes;
+  return BQ_OK;
+}
+
+bq_status_t bq_grouped_plan_info(bq_grouped_plan_t plan, int* tile_config, int* dynamic_schedule, int* work_items) {
+  if (!plan) return fail(BQ_ERR_INVALID_VALUE, "plan is null");
+  if (tile_config) *tile_config = plan->cfg;
+  if (dynamic_schedule) *dynamic_schedule = plan->dyn;
+  if (work_items) *work_items = plan->nitems;
+  return BQ_OK;
+}
+
+bq_status_t bq_grouped_plan_launch(bq_grouped_plan_t plan, void* ws, size_t ws_bytes, bq_stream_t stream) {
+  if (!plan) return fail(BQ_ERR_INVALID_VALUE, "plan is null");
+  bq_status_t st = grouped_check_ws(plan, ws, ws_bytes);
+  if (st != BQ_OK) return st;
+  st = check_handle(plan->h);
+  if (st != BQ_OK) return st;
+  if (plan->count == 0) return BQ_OK;
+  if (!plan->bound || plan->bound_ws != ws) {
+    st = grouped_bind(plan, ws);
+    if (st != BQ_OK) return st;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Tracer tr(plan->h, s, BQ_KERNEL_GROUPED, plan->pr.et >= 0 ? plan->pr.S : plan->cfg, plan->count, plan->nitems, 0,
+            plan->flops, 0.0);
+  hipError_t e = hipGraphLaunch(plan->exec, s);
+  tr.done();
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return BQ_OK;
+}
+
+bq_status_t bq_grouped_plan_autotune(bq_grouped_plan_t plan, void* ws, size_t ws_bytes, bq_stream_t stream) {
+  if (!plan) return fail(BQ_ERR_INVALID_VALUE, "plan is null");
+  bq_status_t st = grouped_check_ws(plan, ws, ws_bytes);
+  if (st != BQ_OK) return st;
+  if (plan->pr.et >= 0 || plan->count == 0) return BQ_OK;
+  st = check_handle(plan->h);
+  if (st != BQ_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(BQ_ERR_HIP, "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(BQ_ERR_HIP, "hipEventCreate");
+  }
+  const int cfgs[2] = {0, 6};
+  float best = 1e30f;
+  int best_cfg = plan->cfg, best_dyn = plan->dyn;
+  for (int c : cfgs) {
+    for (int d = 1; d >= 0; --d) {
+      plan->cfg = c;
+      plan->dyn = d;
+      st = grouped_bind(plan, ws);
+      if (st != BQ_OK) break;
+      hipError_t e = hipGraphLaunch(plan->exec, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = hipGraphLaunch(plan->exec, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "autotune");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_cfg = c;
+        best_dyn = d;
+      }
+    }
+    if (st != BQ_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->cfg = best_cfg;
+  plan->dyn = best_dyn;
+  grouped_release_graph(plan);
+  if (st != BQ_OK) return st;
+  tune_cache_store(plan->tune_key, best_cfg, best_dyn);
+  return grouped_bind(plan, ws);
+}
+
+bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan) {
+  if (!plan) return BQ_OK;
+  grouped_release_graph(plan);
+  if (plan->cap) (void)hipStreamDestroy(plan->cap);
+  if (plan->d_prods) (void)hipFree(plan->d_prods);
+  if (plan->d_items) (void)hipFree(plan->d_items);
+  if (plan->d_counter) (void)hipFree(plan->d_counter);
+  if (plan->d_comb) (void)hipFree(plan->d_comb);
+  if (plan->d_prefix) (void)hipFree(plan->d_prefix);
+  delete plan;
+  return BQ_OK;
 }
 
 }  // extern "C"

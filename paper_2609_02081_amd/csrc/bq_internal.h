@@ -101,6 +101,14 @@ struct SliceGemmArgs {
   int64_t ldc;
 };
 
+// Work item of the batched form: tile (tm, tn) of one problem, whose complex
+// products are prods[prod0 .. prod0 + nprod).
+struct GroupedItem {
+  int prod0;
+  int nprod;
+  int tm, tn;
+};
+
 struct TileConfig {
   int bm, bn, bk, wm, wn;
 };
@@ -112,6 +120,12 @@ hipError_t launch_fill_zero(double* p, int64_t rows, int64_t cols, int64_t ld, h
 int num_tile_configs();
 TileConfig tile_config(int cfg);
 int default_tile_config(int kind, int64_t m, int64_t n, int64_t k);
+// Batched form (complex x complex products only).  cfg: 0 or 6 (tile
+// configurations above); dyn: 1 = device work counter, 0 = cyclic.
+hipError_t launch_grouped(int cfg, int dyn, const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
+                          int blocks, hipStream_t s);
+hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_prefix, int nargs, int64_t total_rows,
+                                  hipStream_t s);
 // Split-precision kernels (bq_split.hip).  et: 0 = BF16 digits (beta 7),
 // 1 = OCP FP8 E4M3 digits (beta 4), 2 = INT8 digits (beta 6).
 hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t s);

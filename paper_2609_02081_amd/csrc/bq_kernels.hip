@@ -62,10 +62,21 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 // LDS keeps the A tile k-major (As[k][i]) and the B tile as stored
 // (Bs[k][j]) so both fragment reads are 16 consecutive doubles per k row.
 // ---------------------------------------------------------------------------
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE>
-__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
-__attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-cgemm_f64(const GemmArgs g) {
+// LDS of one FP64 GEMM tile (double-buffered A and B tiles).
+template <int KIND, int BM, int BN, int BK>
+struct TileSmem {
+  static constexpr int PAD = 4;
+  static constexpr int NA = (KIND == KIND_GAUSS || KIND == KIND_CR) ? 2 : 1;
+  static constexpr int NB = (KIND == KIND_GAUSS || KIND == KIND_RC) ? 2 : 1;
+  double As[2][NA][BK][BM + PAD];
+  __attribute__((aligned(16))) double Bs[2][NB][BK][BN + PAD];
+};
+
+// One output tile (m0, n0) of the complex product described by g: K loop and
+// epilogue.  Every thread of the block must call it (it synchronises).
+template <int KIND, int BM, int BN, int BK, int WM, int WN>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
+                                          TileSmem<KIND, BM, BN, BK>& sm) {
   constexpr int NWN = BN / WN;
   constexpr int NT = (BM / WM) * NWN * 64;
   constexpr int MI = WM / 16, NI = WN / 16;
@@ -83,15 +94,8 @@ cgemm_f64(const GemmArgs g) {
   static_assert(((BN + PAD) * 8) % 16 == 0, "B rows must stay 16-byte aligned in LDS");
 
   // Double-buffered LDS: the A tile k-major (As[k][i]), the B tile as stored.
-  __shared__ double As[2][NA][BK][BM + PAD];
-  __shared__ __attribute__((aligned(16))) double Bs[2][NB][BK][BN + PAD];
-
-  const int tiles_m = (int)((g.m + BM - 1) / BM);
-  const int tiles_n = (int)((g.n + BN - 1) / BN);
-  int tm, tn;
-  tile_coords(tiles_m, tiles_n, g.xcd_remap, g.group_m, tm, tn);
-  const int64_t m0 = (int64_t)tm * BM;
-  const int64_t n0 = (int64_t)tn * BN;
+  auto& As = sm.As;
+  auto& Bs = sm.Bs;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -297,6 +301,18 @@ cgemm_f64(const GemmArgs g) {
       }
 }
 
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+__attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+cgemm_f64(const GemmArgs g) {
+  __shared__ TileSmem<KIND, BM, BN, BK> sm;
+  const int tiles_m = (int)((g.m + BM - 1) / BM);
+  const int tiles_n = (int)((g.n + BN - 1) / BN);
+  int tm, tn;
+  tile_coords(tiles_m, tiles_n, g.xcd_remap, g.group_m, tm, tn);
+  gemm_tile<KIND, BM, BN, BK, WM, WN>(g, (int64_t)tm * BM, (int64_t)tn * BN, sm);
+}
+
 // ---------------------------------------------------------------------------
 // Hadamard pre-combination.  One thread produces two adjacent columns of
 // every requested combination.
@@ -346,6 +362,94 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t rows,
   const int64_t row = blockIdx.x / bpr;
   const int64_t c = (blockIdx.x % bpr) * 256 + threadIdx.x;
   if (row < rows && c < cols) p[row * ld + c] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent products in one launch.
+//
+// grouped_combine: the Hadamard pre-combinations of every problem; block b
+// handles one row of one operand side, found by binary search in the row
+// prefix table.
+// grouped_gemm: persistent blocks take work items (problem, tile) in the
+// given order (largest problems first) from a device counter (dyn = 1) or
+// cyclically (dyn = 0); a work item runs the problem's complex products on
+// its tile one after another, so it alone owns that C tile and the
+// accumulation into C needs no atomics.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) grouped_combine(const CombineArgs* args, const int64_t* row_prefix,
+                                                       int nargs) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = nargs - 1;
+  while (lo < hi) {  // last index with row_prefix[idx] <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (row_prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const CombineArgs& a = args[lo];
+  const int64_t row = b - row_prefix[lo];
+  if (row >= a.rows) return;
+  for (int64_t c = (int64_t)threadIdx.x * 2; c < a.cols; c += 512) {
+    const bool two = (c + 1 < a.cols);
+    double x[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double* src = a.src[u];
+      if (src) {
+        const double* q = src + row * a.lds + c;
+        x[u][0] = q[0];
+        x[u][1] = two ? q[1] : 0.0;
+      } else {
+        x[u][0] = 0.0;
+        x[u][1] = 0.0;
+      }
+    }
+    for (int q = 0; q < a.nq; ++q) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double* d = (h == 0) ? a.dst_r[q] : a.dst_i[q];
+        if (!d) continue;
+        const int o = 4 * h;
+        double v0 = a.w[q][0] * x[o][0];
+        double v1 = a.w[q][0] * x[o][1];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) {
+          v0 = v0 + a.w[q][u] * x[o + u][0];
+          v1 = v1 + a.w[q][u] * x[o + u][1];
+        }
+        double* dd = d + row * a.ldd + c;
+        dd[0] = v0;
+        if (two) dd[1] = v1;
+      }
+    }
+  }
+}
+
+__global__ void reset_counter(int* counter) {
+  if (threadIdx.x == 0) counter[0] = 0;
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int WPE, int DYN>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+__attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter) {
+  __shared__ TileSmem<KIND_GAUSS, BM, BN, BK> sm;
+  __shared__ int next;
+  int it = blockIdx.x;
+  for (;;) {
+    if (DYN) {
+      if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+      __syncthreads();
+      it = next;
+      __syncthreads();
+    }
+    if (it >= nitems) break;
+    const GroupedItem w = items[it];
+    for (int q = 0; q < w.nprod; ++q) {
+      const GemmArgs g = prods[w.prod0 + q];
+      gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN>(g, (int64_t)w.tm * BM, (int64_t)w.tn * BN, sm);
+    }
+    if (!DYN) it += gridDim.x;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -406,6 +510,38 @@ hipError_t launch_cgemm(int kind, const GemmArgs& g, int cfg, hipStream_t s) {
     case KIND_RR: return launch_kind<KIND_RR>(g, cfg, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int WPE>
+static hipError_t launch_grouped_cfg(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
+                                     int dyn, int blocks, hipStream_t s) {
+  constexpr int NT = (BM / WM) * (BN / WN) * 64;
+  if (dyn) {
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
+    hipLaunchKernelGGL((grouped_gemm<BM, BN, BK, WM, WN, WPE, 1>), dim3(blocks), dim3(NT), 0, s, prods, items, nitems,
+                       counter);
+  } else {
+    hipLaunchKernelGGL((grouped_gemm<BM, BN, BK, WM, WN, WPE, 0>), dim3(blocks), dim3(NT), 0, s, prods, items, nitems,
+                       counter);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grouped(int cfg, int dyn, const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
+                          int blocks, hipStream_t s) {
+  switch (cfg) {
+    case 0: return launch_grouped_cfg<64, 64, 16, 32, 32, 2>(prods, items, nitems, counter, dyn, blocks, s);
+    case 6: return launch_grouped_cfg<64, 64, 8, 32, 32, 2>(prods, items, nitems, counter, dyn, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_prefix, int nargs, int64_t total_rows,
+                                  hipStream_t s) {
+  if (total_rows <= 0) return hipSuccess;
+  if (total_rows > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grouped_combine, dim3((unsigned)total_rows), dim3(256), 0, s, args, row_prefix, nargs);
+  return hipGetLastError();
 }
 
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s) {

@@ -1,0 +1,177 @@
+"""Batched form (grouped plans) on the GPU through the C-ABI.
+
+Every product of a batch is checked against the oracle (whole product for
+small sizes, sampled rows/columns including the last ones for large ones)
+and against the single-call result; graph replays, both work schedules,
+workspace re-binding and the split form are covered.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02081_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def bq():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_02081_amd as bq
+
+    bq.lib()
+    return bq
+
+
+def _batch(sizes, seed, dist="uniform"):
+    import torch
+
+    rng = np.random.default_rng(seed)
+    probs = []
+    for (m, k, n) in sizes:
+        A = torch.from_numpy(inputs.blocks(rng, m, k, dist)).to("cuda")
+        B = torch.from_numpy(inputs.blocks(rng, k, n, dist)).to("cuda")
+        C = torch.full((8, m, n), float("nan"), dtype=torch.float64, device="cuda")
+        probs.append((A, B, C))
+    return probs
+
+
+SMALL = [(17, 33, 65), (64, 64, 64), (130, 70, 129), (1, 5, 1), (200, 150, 90), (96, 200, 33),
+         (65, 65, 65), (128, 1, 128), (31, 257, 40), (150, 150, 150), (7, 300, 9), (100, 64, 200)]
+
+
+def test_small_batch_matches_oracle_and_single_calls(bq):
+    import torch
+
+    probs = _batch(SMALL, 61)
+    plan = bq.GroupedPlan(probs)
+    info = plan.info()
+    print(f"grouped small batch: {info}", flush=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (A, B, C), shape in zip(probs, SMALL):
+        a, b, c = A.cpu().numpy(), B.cpu().numpy(), C.cpu().numpy()
+        assert oracle.rel_frobenius(c, oracle.gemm(a, b)) <= TOL, shape
+        single = bq.bq_gemm(A, B)
+        torch.cuda.synchronize()
+        assert oracle.rel_frobenius(c, single.cpu().numpy()) <= 1e-15, shape
+    plan.close()
+
+
+def test_replays_identical_with_eager_work_between(bq):
+    import torch
+
+    probs = _batch(SMALL[:6], 62)
+    plan = bq.GroupedPlan(probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    first = [C.cpu().numpy().copy() for (_, _, C) in probs]
+    x = torch.randn(512, 512, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        for (_, _, C) in probs:
+            C.fill_(float("nan"))
+        y = (x @ x).sum()  # unrelated eager work between replays
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).item()
+        for f, (_, _, C) in zip(first, probs):
+            assert np.array_equal(C.cpu().numpy(), f), rep
+    plan.close()
+
+
+def test_autotune_both_schedules_and_rebind(bq, tmp_path, monkeypatch):
+    import torch
+
+    monkeypatch.setenv("BQ_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    probs = _batch(SMALL, 63)
+    plan = bq.GroupedPlan(probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    ref = [C.cpu().numpy().copy() for (_, _, C) in probs]
+    plan.autotune()
+    chosen = plan.info()
+    print(f"autotune chose {chosen}", flush=True)
+    for (_, _, C) in probs:
+        C.fill_(0.0)
+    # a different workspace buffer re-records the graph
+    ws2 = torch.empty(max(1, plan.workspace_size()), dtype=torch.uint8, device="cuda")
+    plan.launch(workspace=ws2)
+    torch.cuda.synchronize()
+    for r, (_, _, C) in zip(ref, probs):
+        assert oracle.rel_frobenius(C.cpu().numpy(), r) <= 1e-15
+    plan.close()
+    # the cache file now holds the choice; a new plan with the same sizes reads it
+    text = (tmp_path / "tune.txt").read_text()
+    assert text.strip()
+    plan2 = bq.GroupedPlan(probs)
+    assert plan2.info()["tile_config"] == chosen["tile_config"]
+    assert plan2.info()["dynamic"] == chosen["dynamic"]
+    plan2.close()
+
+
+def _sample(n, r, seed):
+    rng = np.random.default_rng(seed)
+    if n <= r:
+        return np.arange(n)
+    idx = np.sort(rng.choice(n - 1, size=r - 1, replace=False))
+    return np.append(idx, n - 1)
+
+
+def test_512_products_log_uniform(bq):
+    """512 products, sizes log-uniform over 64..1536 (seed 5), uniform[-1,1]."""
+    import torch
+
+    sizes = inputs.batch_sizes(512, 64, 1536, seed=5)
+    print(f"512 products: total n^3 = {sum(n ** 3 for n in sizes):.3e}", flush=True)
+    probs = []
+    for i, n in enumerate(sizes):
+        A = inputs.device_uniform(n, n, 1000 + 2 * i, "cuda")
+        B = inputs.device_uniform(n, n, 1001 + 2 * i, "cuda")
+        probs.append((A, B, torch.empty_like(A)))
+    plan = bq.GroupedPlan(probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    print("512 products: launched", flush=True)
+    worst = 0.0
+    for i, ((A, B, C), n) in enumerate(zip(probs, sizes)):
+        rows, cols = _sample(n, 16, 7 * i), _sample(n, 16, 7 * i + 1)
+        ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+        err = oracle.rel_frobenius(C[:, ri][:, :, ci].cpu().numpy(),
+                                   oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy()))
+        worst = max(worst, err)
+    print(f"512 products: worst sampled rel err {worst:.3e}", flush=True)
+    assert worst <= TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_int8"])
+def test_split_batch(bq, prec):
+    import torch
+
+    probs = _batch(SMALL[:8], 64)
+    plan = bq.GroupedPlan(probs, prec=prec)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (A, B, C), shape in zip(probs, SMALL):
+        err = oracle.rel_frobenius(C.cpu().numpy(), oracle.gemm(A.cpu().numpy(), B.cpu().numpy()))
+        assert err <= TOL, (shape, err)
+    plan.close()
+
+
+def test_rejects_overlapping_outputs(bq):
+    import torch
+
+    A = torch.rand(8, 32, 32, dtype=torch.float64, device="cuda")
+    B = torch.rand(8, 32, 32, dtype=torch.float64, device="cuda")
+    C = torch.empty(8, 32, 32, dtype=torch.float64, device="cuda")
+    with pytest.raises(bq.BqError) as e:
+        bq.GroupedPlan([(A, B, C), (B, A, C)])
+    assert e.value.code == 3
+    Amask = A.clone()
+    with pytest.raises(bq.BqError) as e:
+        bq.GroupedPlan([([Amask[0]] + [None] * 7, B, C)])
+    assert e.value.code == 2
