@@ -100,6 +100,54 @@ def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, copy_bytes
     print(json.dumps(out))
 
 
+def batched_leg(bq, inputs, torch, count, log):
+    """count products, square sizes log-uniform over 64..1536 (seed 5),
+    uniform[-1, 1]: one grouped plan (graph of a pre-combination launch and
+    a persistent launch, autotuned) against a loop of single calls."""
+    sizes = inputs.batch_sizes(count, 64, 1536, seed=5)
+    probs = []
+    for i, m in enumerate(sizes):
+        A = inputs.device_uniform(m, m, 1000 + 2 * i, "cuda")
+        B = inputs.device_uniform(m, m, 1001 + 2 * i, "cuda")
+        probs.append((A, B, torch.empty_like(A)))
+    flop_exec = sum(24 * 2.0 * m ** 3 for m in sizes)
+    flop_eff = flop_exec * 64 / 24
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t0 = time.time()
+    plan = bq.GroupedPlan(probs)
+    plan.autotune()
+    tune_s = time.time() - t0
+    g_ms = timed(plan.launch, 3)
+    info = plan.info()
+    plan.close()
+    big = max(sizes)
+    res, _ = bq.workspace_size(big, big, big)
+    ws = torch.empty(res, dtype=torch.uint8, device="cuda")
+
+    def loop():
+        for (A, B, C) in probs:
+            bq.bq_gemm(A, B, C, workspace=ws)
+    l_ms = timed(loop, 2)
+    log(f"batched: grouped {g_ms:.1f} ms, loop {l_ms:.1f} ms")
+    return {"workload": f"{count} products, n log-uniform over 64..1536 (seed 5), uniform[-1,1], FP64",
+            "grouped_ms": round(g_ms, 2), "grouped_eff_tflops": round(flop_eff / (g_ms * 1e-3) / 1e12, 2),
+            "grouped_exec_tflops": round(flop_exec / (g_ms * 1e-3) / 1e12, 2),
+            "loop_ms": round(l_ms, 2), "loop_eff_tflops": round(flop_eff / (l_ms * 1e-3) / 1e12, 2),
+            "speedup_vs_loop": round(l_ms / g_ms, 3), "plan": info, "plan_create_and_autotune_s": round(tune_s, 2)}
+
+
 def sample_idx(n, r, seed):
     import numpy as np
 
@@ -117,6 +165,10 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="rows/cols of the sub-block the oracle recomputes (0: skip)")
+    ap.add_argument("--split", default="split_int8,split_bf16,split_fp8",
+                    help="split-precision forms timed beside FP64 on the same inputs ('' to skip)")
+    ap.add_argument("--batched", type=int, default=512,
+                    help="products in the batched leg (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates the HBM counters)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
@@ -171,7 +223,6 @@ def main():
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     recs = bq.trace_read()
-    bq.trace_enable(False)
     log(f"timed {args.steps} steps: {total_ms:.1f} ms")
 
     ms = total_ms / args.steps
@@ -198,23 +249,82 @@ def main():
                "achieved_GBs": round(c_bytes / (c_ms * 1e-3) / 1e9, 1) if c_ms > 0 else None,
                "peak_GBs": PEAK_HBM_GBS, "launches": len(comb)}
 
-    cpu = None
-    rel_err = None
-    if args.cpu_sample > 0:
-        import oracle
-
-        r = args.cpu_sample
+    # Sampled sub-block (rows R, columns S, the last row and column always
+    # included) of every result, for the CPU baseline leg below.
+    r = args.cpu_sample
+    samples = {}
+    if r > 0:
         rows, cols = sample_idx(n, r, 101), sample_idx(n, r, 102)
         ri = torch.as_tensor(rows, device=dev)
         ci = torch.as_tensor(cols, device=dev)
+        take = lambda: C[:, ri][:, :, ci].cpu().numpy()
+        samples["fp64"] = take()
+
+    # Split-precision forms on the same inputs: one timed product each at the
+    # default slice count.
+    split = {}
+    if args.split:
+        del ws
+        torch.cuda.empty_cache()
+        # Slice count: start at the library default and add slices until the
+        # sampled result agrees with the FP64 result (itself ~1e-14 from the
+        # oracle) to 5e-13; the error reported is then the oracle's.
+        max_s = {"split_bf16": 8, "split_fp8": 14, "split_int8": 9}
+        start_s = {"split_bf16": 7, "split_fp8": 13, "split_int8": 8}
+        for prec in [x for x in args.split.split(",") if x]:
+            tried = []
+            S = start_s[prec]
+            while True:
+                sres, _ = bq.workspace_size(n, n, n, prec=prec, slices=S)
+                sws = torch.empty(sres, dtype=torch.uint8, device=dev)
+                bq.trace_read()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                bq.bq_gemm(A, B, C, prec=prec, slices=S, workspace=sws)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                sms = e0.elapsed_time(e1)
+                srecs = bq.trace_read()
+                del sws
+                torch.cuda.empty_cache()
+                cs = take() if r > 0 else None
+                d = (float(np.linalg.norm(cs - samples["fp64"]) / np.linalg.norm(samples["fp64"]))
+                     if r > 0 else None)
+                tried.append({"slices": S, "ms": round(sms, 1), "rel_diff_vs_fp64_sample": d})
+                log(f"{prec} S={S}: {sms:.1f} ms, rel diff vs FP64 {d}")
+                if d is None or d <= 5e-13 or S >= max_s[prec]:
+                    break
+                S += 1
+            sg = [x for x in srecs if x["kernel"] == "slice_gemm"]
+            sg_ms = sum(x["ms"] for x in sg)
+            split[prec] = {"slices": S, "ms": round(sms, 2),
+                           "eff_tflops": round(flop_eff / (sms * 1e-3) / 1e12, 3),
+                           "speed_vs_fp64": round(ms / sms, 3), "rel_err_sampled_vs_oracle": None,
+                           "slice_gemm_lowprec_tflops": round(sum(x["flops"] for x in sg) / (sg_ms * 1e-3) / 1e12, 1)
+                           if sg_ms > 0 else None,
+                           "split_kernels_ms": round(sum(x["ms"] for x in srecs if x["kernel"] == "split"), 2),
+                           "tried": tried}
+            if r > 0:
+                samples[prec] = cs
+    bq.trace_enable(False)
+
+    # CPU baseline leg: the oracle, timed on the sampled sub-block with the
+    # full k, on the host's cores; it also scores every sampled result.
+    cpu = None
+    rel_err = None
+    if r > 0:
+        import oracle
+
         As = A[:, ri, :].cpu().numpy()
         Bs = B[:, :, ci].cpu().numpy()
-        Cs = C[:, ri][:, :, ci].cpu().numpy()
         log(f"oracle on a {r}x{r} sampled sub-block (k = {n}) with {oracle.num_threads()} threads")
         t0 = time.perf_counter()
         ref = oracle.gemm(As, Bs)
         t_cpu = time.perf_counter() - t0
-        rel_err = oracle.rel_frobenius(Cs, ref)
+        rel_err = oracle.rel_frobenius(samples["fp64"], ref)
+        for prec in split:
+            split[prec]["rel_err_sampled_vs_oracle"] = oracle.rel_frobenius(samples[prec], ref)
         cpu = {"value": round(64 * 2.0 * r * r * n / t_cpu / 1e12, 6),
                "unit": "effective TFLOP/s (64 real GEMMs counted)", "cores": oracle.num_threads(),
                "kind": "oracle",
@@ -222,6 +332,12 @@ def main():
                          f"of the n={n} product, full k={n}: {t_cpu:.2f} s",
                "seconds": round(t_cpu, 3)}
         log(f"oracle {t_cpu:.1f}s, sampled rel Frobenius error {rel_err:.3e}")
+
+    batched = None
+    if args.batched > 0:
+        del A, B, C
+        torch.cuda.empty_cache()
+        batched = batched_leg(bq, inputs, torch, args.batched, log)
 
     out = {"metric": METRIC, "value": round(eff_tflops, 3), "unit": "effective TFLOP/s (64 real GEMMs counted)",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -233,7 +349,8 @@ def main():
            "executed_tflops": round(exec_tflops, 3),
            "mfma_frac_of_fp64_peak": round(exec_tflops / PEAK_FP64_TFLOPS, 4),
            "rel_err_sampled_vs_oracle": rel_err,
-           "roofline": roofline, "combine": combine, "cpu_baseline": cpu}
+           "roofline": roofline, "combine": combine, "cpu_baseline": cpu,
+           "split_precision": split, "batched": batched}
     print(json.dumps(out), flush=True)
 
 

@@ -222,8 +222,8 @@ void workspace_need(const Plan& pl, const Prec& pr, int64_t m, int64_t n, int64_
   bool any = false;
   for (const Prod& p : pl.prods) any |= (p.L.combo >= 0);
   if (pl.bilinear && any) {
-    const size_t a1 = align256(size_t(m) * size_t(k) * 8);
-    const size_t b1 = align256(size_t(k) * size_t(n) * 8);
+    const size_t a1 = align256(size_t(m) * size_t(round_up(k, 8)) * 8);
+    const size_t b1 = align256(size_t(k) * size_t(round_up(n, 8)) * 8);
     const size_t per_q = (pl.combA_r + pl.combA_i) * a1 + (pl.combB_r + pl.combB_i) * b1;
     *resident = 4 * per_q;
     *minimum = per_q;
@@ -385,7 +385,7 @@ int tile_override() {
   const char* e = std::getenv("BQ_TILE_CONFIG");
   if (!e || !*e) return -1;
   const int v = std::atoi(e);
-  return (v >= 0 && v < bq::num_tile_configs()) ? v : -1;
+  return (v >= 0 && v < bq::num_tile_configs() && bq::tile_config(v).bm > 0) ? v : -1;
 }
 
 bq_status_t hip_fail(hipError_t e, const char* what) {
@@ -430,9 +430,11 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   bool touched[8] = {};
   const int cfg_override = tile_override();
 
-  // Workspace slots for the pre-combined operands.
-  const size_t a1 = align256(size_t(m) * size_t(k) * 8);
-  const size_t b1 = align256(size_t(k) * size_t(n) * 8);
+  // Workspace slots for the pre-combined operands (rows padded to whole
+  // 64-byte lines so the GEMM takes its aligned 16-byte load path).
+  const int64_t kpad = round_up(k, 8), npad = round_up(n, 8);
+  const size_t a1 = align256(size_t(m) * size_t(kpad) * 8);
+  const size_t b1 = align256(size_t(k) * size_t(npad) * 8);
   char* wp = static_cast<char*>(ws);
   double* cA_r[4] = {};
   double* cA_i[4] = {};
@@ -518,7 +520,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     ca.lds = X->ld;
     ca.rows = left ? m : k;
     ca.cols = left ? k : n;
-    ca.ldd = ca.cols;
+    ca.ldd = left ? kpad : npad;
     ca.nq = nq;
     int nsrc = 0, ndst = 0;
     for (int c = 0; c < 8; ++c) nsrc += (ca.src[c] != nullptr);
@@ -553,10 +555,10 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       }
       L.r = L.r ? cA_r[slot] : nullptr;
       L.i = L.i ? cA_i[slot] : nullptr;
-      L.ld = k;
+      L.ld = kpad;
       R.r = R.r ? cB_r[slot] : nullptr;
       R.i = R.i ? cB_i[slot] : nullptr;
-      R.ld = n;
+      R.ld = npad;
     }
     // Imaginary-only operands: (i s x) as a real operand x times i s.
     Cplx rot = {1.0, 0.0};
@@ -936,7 +938,8 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
       const Plan& pl = p->plans[pi];
       const int64_t m = q.A.rows, n = q.B.cols, k = q.A.cols;
       char* wp = static_cast<char*>(ws) + p->ws_off[pi];
-      const size_t a1 = align256(size_t(m) * size_t(k) * 8), b1 = align256(size_t(k) * size_t(n) * 8);
+      const int64_t kpad = round_up(k, 8), npad = round_up(n, 8);
+      const size_t a1 = align256(size_t(m) * size_t(kpad) * 8), b1 = align256(size_t(k) * size_t(npad) * 8);
       double *cAr[4], *cAi[4], *cBr[4], *cBi[4];
       for (int c = 0; c < 4; ++c) {
         cAr[c] = reinterpret_cast<double*>(wp); wp += a1;
@@ -951,7 +954,7 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
         ca.lds = X.ld;
         ca.rows = side == 0 ? m : k;
         ca.cols = side == 0 ? k : n;
-        ca.ldd = ca.cols;
+        ca.ldd = side == 0 ? kpad : npad;
         ca.nq = 4;
         for (int j = 0; j < 4; ++j) {
           ca.dst_r[j] = side == 0 ? cAr[j] : cBr[j];
@@ -967,8 +970,8 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
       for (const Prod& pd : pl.prods) {
         Operand L = pd.L, R = pd.R;
         if (L.combo >= 0) {
-          L.r = cAr[L.combo]; L.i = cAi[L.combo]; L.ld = k;
-          R.r = cBr[R.combo]; R.i = cBi[R.combo]; R.ld = n;
+          L.r = cAr[L.combo]; L.i = cAi[L.combo]; L.ld = kpad;
+          R.r = cBr[R.combo]; R.i = cBi[R.combo]; R.ld = npad;
         }
         bq::GemmArgs g{};
         g.lr = L.r; g.li = L.i; g.lda = L.ld;

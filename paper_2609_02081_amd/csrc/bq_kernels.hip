@@ -110,8 +110,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   const double* pb[2] = {g.rr + n0, HAS_RI ? g.ri + n0 : nullptr};
   const int64_t mrem = g.m - m0;
   const int64_t nrem = g.n - n0;
-  // Interior tiles with 16-byte aligned rows load without bounds checks.
-  const bool fast = g.vec && mrem >= BM && nrem >= BN;
+  // Interior tiles load without bounds checks (16-byte loads when the rows
+  // are 16-byte aligned).
+  const bool interior = mrem >= BM && nrem >= BN;
+  const bool fast = g.vec && interior;
 
   double ra[NA][2 * A_PAIRS];
   double rb[NB][2 * B_PAIRS];
@@ -141,6 +143,33 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
           const d2 x = *reinterpret_cast<const d2*>(base + (uint32_t)(r * (uint32_t)g.ldb + c));
           rb[p][2 * i] = x[0];
           rb[p][2 * i + 1] = x[1];
+        }
+      }
+    } else if (interior && kfull) {
+      // Interior tile whose rows are not 16-byte aligned: the same pattern
+      // with 8-byte loads, still without bounds checks.
+#pragma unroll
+      for (int p = 0; p < NA; ++p) {
+        const double* base = pa[p] + k0;
+#pragma unroll
+        for (int i = 0; i < A_PAIRS; ++i) {
+          const int v = tid + i * NT;
+          const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
+          const uint32_t off = (uint32_t)(r * (uint32_t)g.lda + c);
+          ra[p][2 * i] = base[off];
+          ra[p][2 * i + 1] = base[off + 1];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NB; ++p) {
+        const double* base = pb[p] + k0 * g.ldb;
+#pragma unroll
+        for (int i = 0; i < B_PAIRS; ++i) {
+          const int v = tid + i * NT;
+          const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
+          const uint32_t off = (uint32_t)(r * (uint32_t)g.ldb + c);
+          rb[p][2 * i] = base[off];
+          rb[p][2 * i + 1] = base[off + 1];
         }
       }
     } else {
@@ -460,8 +489,8 @@ static const TileConfig kConfigs[] = {
     {64, 64, 16, 32, 32},    // 1: 4 waves, 1 wave / SIMD
     {128, 64, 16, 64, 32},   // 2: 4 waves, 1 wave / SIMD
     {64, 64, 32, 32, 32},    // 3: 4 waves, 2 waves / SIMD
-    {128, 128, 8, 64, 32},   // 4: 8 waves, 2 waves / SIMD
-    {128, 128, 16, 64, 64},  // 5: 4 waves, 1 wave / SIMD
+    {0, 0, 0, 0, 0},         // 4: retired (spilled)
+    {0, 0, 0, 0, 0},         // 5: retired (spilled)
     {64, 64, 8, 32, 32},     // 6: 4 waves, 2 waves / SIMD
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
@@ -495,8 +524,6 @@ static hipError_t launch_kind(const GemmArgs& g, int cfg, hipStream_t s) {
     case 1: return launch_one<KIND, 64, 64, 16, 32, 32, 1>(g, s);
     case 2: return launch_one<KIND, 128, 64, 16, 64, 32, 1>(g, s);
     case 3: return launch_one<KIND, 64, 64, 32, 32, 32, 2>(g, s);
-    case 4: return launch_one<KIND, 128, 128, 8, 64, 32, 2>(g, s);
-    case 5: return launch_one<KIND, 128, 128, 16, 64, 64, 1>(g, s);
     case 6: return launch_one<KIND, 64, 64, 8, 32, 32, 2>(g, s);
     default: return hipErrorInvalidValue;
   }

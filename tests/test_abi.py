@@ -124,8 +124,9 @@ def test_alias_detection():
 def test_workspace_sizes_and_errors():
     m, n, k = 100, 60, 40
     res, mn = ws_need(m, n, k)
-    a1 = (m * k * 8 + 255) // 256 * 256
-    b1 = (k * n * 8 + 255) // 256 * 256
+    up8 = lambda x: (x + 7) // 8 * 8      # combination buffers: rows padded to 64 bytes
+    a1 = (m * up8(k) * 8 + 255) // 256 * 256
+    b1 = (k * up8(n) * 8 + 255) // 256 * 256
     assert res == 4 * (2 * a1 + 2 * b1) and mn == 2 * a1 + 2 * b1
     rq_res, rq_min = ws_need(m, n, k, 0x0F, 0x0F)
     assert rq_res == 4 * (a1 + b1) and rq_min == a1 + b1
