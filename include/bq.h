@@ -61,7 +61,8 @@ typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
  * (BF16, FP8) or int32 (INT8) sums, keep the slice pairs with s + t <=
  * slices + 1, and accumulate and rescale in FP64.  Digit types: BF16
  * (beta 7, slices 1..8, default 7), OCP FP8 E4M3 (beta 4, slices 1..14,
- * default 13), INT8 (beta 6, slices 1..9, default 8).  The Hadamard and
+ * default 13), INT8 (beta 7 with one bit of exponent headroom, so the
+ * leading digit fits a signed byte; slices 1..9, default 7).  The Hadamard and
  * Gauss pre-combinations and the post-combination stay FP64. */
 typedef enum {
   BQ_PREC_FP64 = 0,

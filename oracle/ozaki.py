@@ -6,8 +6,11 @@ The paper computes every real GEMM in FP64; the split form is an extension
 (error-free splitting of Ozaki, Ogita, Oishi and Rump, 2012), read here as:
 
 * left factor X (m x k): per row i an exponent e_i, the frexp exponent of
-  max_j |x_ij| (so |x_ij| 2^-e_i < 1); right factor Y (k x n): per column j
-  an exponent f_j;
+  max_j |x_ij| plus a headroom h (so |x_ij| 2^-e_i < 2^-h); right factor
+  Y (k x n): per column j an exponent f_j;  h = 1 for INT8 digits (beta 7:
+  without it the leading digit could reach 2^7 = 128, one past a signed
+  byte), h = 0 for BF16 (beta 7) and FP8 E4M3 (beta 4), whose leading digit
+  2^beta is representable;
 * digits of y = x 2^-e: q_1 = rint(2^b y), y_1 = y - q_1 2^-b, and
   q_s = rint(2^{bs} y_{s-1}), y_s = y_{s-1} - q_s 2^{-bs} for s = 2..S;
 * T = diag(2^e) [ sum_{s + t <= S + 1} 2^{-b(s+t)} Q_s R_t ] diag(2^f).
@@ -18,22 +21,23 @@ path only by FP64 summation order.
 """
 import numpy as np
 
-BETA = {"bf16": 7, "fp8": 4, "int8": 6}
+BETA = {"bf16": 7, "fp8": 4, "int8": 7}
+HEAD = {"bf16": 0, "fp8": 0, "int8": 1}
 
 
-def exponents(X, axis):
-    """frexp exponent of the largest magnitude along `axis` (rows: axis=1);
-    all-zero lines get None (their digits are zero)."""
+def exponents(X, axis, head=0):
+    """frexp exponent of the largest magnitude along `axis` (rows: axis=1),
+    plus `head`; all-zero lines get 0 (their digits are zero)."""
     mx = np.max(np.abs(X), axis=axis)
     _, e = np.frexp(mx)
-    return np.where(mx > 0, e, 0).astype(np.int64), mx > 0
+    return np.where(mx > 0, e + head, 0).astype(np.int64), mx > 0
 
 
-def digits(X, beta, S, axis):
+def digits(X, beta, S, axis, head=0):
     """Digit slices Q[s] (int64) and exponents of X along `axis`
     (axis=1: one exponent per row, the left factor; axis=0: per column)."""
     X = np.asarray(X, dtype=np.float64)
-    e, nz = exponents(X, axis)
+    e, nz = exponents(X, axis, head)
     ee = e[:, None] if axis == 1 else e[None, :]
     y = np.ldexp(X, -ee)
     Q = []
@@ -46,9 +50,9 @@ def digits(X, beta, S, axis):
 
 def product(X, Y, kind="bf16", S=7):
     """Split-form real product X @ Y."""
-    beta = BETA[kind]
-    QX, ex, _ = digits(X, beta, S, axis=1)
-    QY, ey, _ = digits(Y, beta, S, axis=0)
+    beta, head = BETA[kind], HEAD[kind]
+    QX, ex, _ = digits(X, beta, S, axis=1, head=head)
+    QY, ey, _ = digits(Y, beta, S, axis=0, head=head)
     acc = np.zeros((X.shape[0], Y.shape[1]), dtype=np.float64)
     for d in range(2, S + 2):
         lvl = np.zeros_like(acc, dtype=np.int64)

@@ -2,7 +2,8 @@
 
 Every call recompiles.  Flags: -O3, C++17, and -packed-fp32-ops disabled for
 the device code (hipcc's host pass warns that it does not know the feature;
-that warning is harmless).
+that warning is harmless); the slice GEMMs also keep MFMA accumulators in
+VGPRs (EXTRA).
 """
 import os
 import subprocess
@@ -18,6 +19,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+# Slice GEMMs: MFMA accumulators in ordinary VGPRs.  The level sums are
+# updated by chains of MFMAs of different lengths; with AGPR accumulators the
+# register allocator rotates them between registers and copies them back
+# every k-step, with VGPR accumulators every MFMA accumulates in place.
+EXTRA = {"bq_split.hip": ["-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _run(cmd, verbose):
@@ -38,7 +44,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        _run([HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        _run([HIPCC, *COMMON, *EXTRA.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)

@@ -187,7 +187,7 @@ struct Prec {
   int S = 0;
 };
 
-constexpr int kDefaultSlices[3] = {7, 13, 8};
+constexpr int kDefaultSlices[3] = {7, 13, 7};
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -373,12 +373,22 @@ void tile_order(int* xcd, int* group) {
   }
 }
 
-// Slice-GEMM block shape (BQ_SLICE_VARIANT = 0 or 1 overrides the default).
+// Slice-GEMM block shape (BQ_SLICE_VARIANT = 0 .. 3 overrides the default).
 int slice_variant() {
   const char* e = std::getenv("BQ_SLICE_VARIANT");
   if (!e || !*e) return -1;
   const int v = std::atoi(e);
-  return (v == 0 || v == 1) ? v : -1;
+  return (v >= 0 && v <= 3) ? v : -1;
+}
+
+// BQ_SLICE_FLUSH = f > 0 flushes the level sums at least every f k-steps
+// (never less often than exactness allows).
+int slice_flush(int et, int S) {
+  const int bound = bq::slice_flush_steps(et, S);
+  const char* e = std::getenv("BQ_SLICE_FLUSH");
+  if (!e || !*e) return bound;
+  const int v = std::atoi(e);
+  return v > 0 ? std::min(v, bound) : bound;
 }
 
 int tile_override() {
@@ -461,7 +471,8 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     exp_b = reinterpret_cast<int*>(wp); wp += sl.eb_bytes;
   }
   const int es = pr.et == 0 ? 2 : 1;
-  const int beta = pr.et == 0 ? 7 : (pr.et == 1 ? 4 : 6);
+  const int beta = pr.et >= 0 ? bq::slice_beta(pr.et) : 0;
+  const int head = pr.et >= 0 ? bq::slice_head(pr.et) : 0;
 
   // One real product T = X Y of the split form, X = xw1 x1 + xw2 x2 (m x k),
   // Y = yw1 y1 + yw2 y2 (k x n); C_w op= cw * T for each (w, cw).
@@ -478,8 +489,10 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       ++sg.ntgt;
     }
     if (sg.ntgt == 0) return hipSuccess;
-    bq::SplitArgs xa{x1, x2, xw1, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp, sl.rows_pad * sl.kp, beta, 1};
-    bq::SplitArgs ya{y1, y2, yw1, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp, sl.cols_pad * sl.kp, beta, 0};
+    const int variant = bq::resolve_slice_variant(pr.et, pr.S, slice_variant());
+    const int tiled = bq::slice_variant_tiled(variant) ? 1 : 0;
+    bq::SplitArgs xa{x1, x2, xw1, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp, sl.rows_pad * sl.kp, beta, head, 1, tiled};
+    bq::SplitArgs ya{y1, y2, yw1, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp, sl.cols_pad * sl.kp, beta, head, 0, tiled};
     const double elems_x = double(m) * double(k), elems_y = double(k) * double(n);
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
@@ -505,10 +518,11 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     sg.m = m;
     sg.n = n;
     sg.beta = beta;
+    sg.kflush = slice_flush(pr.et, pr.S);
     sg.ldc = C->ld;
     const double pairs = double(pr.S) * double(pr.S + 1) / 2.0;
     Tracer tr(h, s, BQ_KERNEL_SLICE_GEMM, pr.S, m, n, k, pairs * 2.0 * double(m) * double(n) * double(k), 0.0);
-    hipError_t e = bq::launch_slice_gemm(pr.et, pr.S, slice_variant(), sg, s);
+    hipError_t e = bq::launch_slice_gemm(pr.et, pr.S, variant, sg, s);
     tr.done();
     return e;
   };

@@ -79,7 +79,9 @@ struct SplitArgs {
   int64_t kp;                  // reduced dimension padded to 64 (zero digits)
   int64_t slice_stride;        // elements between consecutive slices
   int beta;                    // digit width in bits
+  int head;                    // exponent headroom: row/column exponent = frexp exponent + head
   int left;
+  int tiled;                   // digit layout: 0 = D[s][row][kk]; 1 = 64-row x one-k-step tiles (slice_tile_offset)
 };
 
 constexpr int kMaxSliceTargets = 8;
@@ -94,6 +96,7 @@ struct SliceGemmArgs {
   const int* eb;  // column exponents of the right operand
   int64_t m, n;
   int beta;
+  int kflush;  // k-steps whose level sums stay exact before they go to FP64
   int ntgt;
   double* c[kMaxSliceTargets];
   double coef[kMaxSliceTargets];
@@ -127,11 +130,16 @@ hipError_t launch_grouped(int cfg, int dyn, const GemmArgs* prods, const Grouped
 hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_prefix, int nargs, int64_t total_rows,
                                   hipStream_t s);
 // Split-precision kernels (bq_split.hip).  et: 0 = BF16 digits (beta 7),
-// 1 = OCP FP8 E4M3 digits (beta 4), 2 = INT8 digits (beta 6).
+// 1 = OCP FP8 E4M3 digits (beta 4), 2 = INT8 digits (beta 7, headroom 1).
 hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t s);
 hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t s);  // variant -1: default
+int resolve_slice_variant(int et, int S, int variant);  // the shape launch_slice_gemm runs
+bool slice_variant_tiled(int variant);                   // digits must be written tiled
 int max_slices(int et);
 int slice_block_rows(int et, int S);  // rows of a slice-GEMM block tile (128 or 64)
 int slice_kstep(int et);              // k per MFMA step (32 or 64)
+int slice_beta(int et);
+int slice_head(int et);
+int slice_flush_steps(int et, int S);  // k-steps per exact level accumulation
 
 }  // namespace bq

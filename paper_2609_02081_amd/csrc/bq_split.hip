@@ -3,20 +3,24 @@
 // A real FP64 product T = X Y (X m x k, Y k x n) is computed from
 // low-precision slices:
 //   * every row i of X gets a power-of-two exponent e_i (the frexp exponent
-//     of its largest magnitude), every column j of Y an exponent f_j;
-//   * x_ij 2^-e_i in (-1, 1) is written as S signed digits,
+//     of its largest magnitude, plus h), every column j of Y an exponent f_j;
+//   * x_ij 2^-e_i in (-2^-h, 2^-h) is written as S signed digits,
 //     q_1 = rint(2^b y), y_1 = y - q_1 2^-b, q_s = rint(2^{bs} y_{s-1}), ...
-//     so x = 2^e_i (sum_s q_s 2^{-bs} + remainder), |q_1| <= 2^b,
-//     |q_s| <= 2^{b-1}; the digits are small integers, exact in BF16 (b = 7),
-//     OCP FP8 E4M3 (b = 4) or INT8 (b = 6);
+//     so x = 2^e_i (sum_s q_s 2^{-bs} + remainder), |q_1| <= 2^{b-h},
+//     |q_s| <= 2^{b-1}; the digits are small integers, exact in BF16 (b = 7,
+//     h = 0), OCP FP8 E4M3 (b = 4, h = 0) or INT8 (b = 7, h = 1: one bit of
+//     headroom keeps the leading digit inside a signed byte);
 //   * T_ij = 2^{e_i + f_j} sum_{d = 2}^{S+1} 2^{-bd} sum_{s + t = d} (Q_s R_t)_ij
 //     (pairs with s + t > S + 1 are dropped).
-// Each level d is accumulated by MFMA over one k-step (32 deep in FP32 for
-// BF16/FP8: at most S * 32 * 2^{2b} < 2^24, so every partial sum is an exact
-// integer; 64 deep in int32 for INT8) and then added, scaled by 2^{-bd},
-// into FP64 accumulators.  Only
-// the splitting, the exponent scaling and the level accumulation are FP64.
+// Each level d is accumulated by MFMA in FP32 (BF16/FP8) or int32 (INT8)
+// over as many k-steps as keep every partial sum an exact integer (the bound
+// is in slice_flush_steps), then added, scaled by 2^{-bd}, into FP64
+// accumulators.  Only the splitting, the exponent scaling and the level
+// accumulation are FP64.
 #include <limits.h>
+
+#include <algorithm>
+#include <cmath>
 
 #include "bq_internal.h"
 
@@ -53,6 +57,7 @@ __global__ void __launch_bounds__(256) split_exp_left(const SplitArgs a, int* ex
     const int64_t c = c0 + j;
     if (c < a.cols) e = max(e, exp_of(operand_value(a, r * a.ld + c)));
   }
+  if (e != INT_MIN) e += a.head;
   for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
   __shared__ int red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
@@ -77,13 +82,38 @@ __global__ void __launch_bounds__(256) split_exp_right(const SplitArgs a, int* e
   __syncthreads();
   if (threadIdx.x < 64) {
     e = max(max(red[threadIdx.x], red[threadIdx.x + 64]), max(red[threadIdx.x + 128], red[threadIdx.x + 192]));
-    if (c < a.cols && e != INT_MIN) atomicMax(&exps[c], e);
+    if (c < a.cols && e != INT_MIN) atomicMax(&exps[c], e + a.head);
   }
 }
 
 __global__ void __launch_bounds__(256) fill_int(int* p, int64_t n, int v) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// Chunk position of logical chunk ch in tile row r (rows of 4 chunks).
+// 16-byte chunks (rows of 64 bytes): a 16-byte LDS access is served 8 lanes
+// at a time over 32 banks (128 bytes); a fragment read has 8 lanes on 8
+// consecutive rows at one logical chunk, and rows 2j, 2j + 1 share a
+// 128-byte bank line offset by 64 bytes, so even rows must take 4 distinct
+// positions, and odd rows too: position = ch ^ f(r) with f built from row
+// bits 1..3.  8-byte chunks (rows of 32 bytes): 16 lanes per access on 16
+// consecutive rows; rows r and r + 4 share banks, so f = bits 2..3.
+template <int CH>
+__device__ __forceinline__ int swz_chunk(int r, int ch) {
+  if constexpr (CH == 16) return ch ^ ((((r >> 1) ^ (r >> 3)) & 1) | ((r >> 1) & 2));
+  else return ch ^ ((r >> 2) & 3);
+}
+
+// Tiled digit layout (direct-to-LDS slice GEMM, 64-byte tile rows): within
+// one slice, the 64 rows x one k-step (BK elements, 64 bytes) of row tile
+// rt, k-step kt form one 4 KB block at (rt * nk + kt) * 4096, stored in the
+// LDS order (row r at r * 64, logical chunk ch at position swz_chunk(r, ch)),
+// so that a straight 4 KB copy lands the tile ready for fragment reads.
+__device__ __forceinline__ int64_t slice_tile_offset(int64_t r, int64_t byte_in_row, int64_t row_bytes) {
+  const int64_t nk = row_bytes >> 6, kt = byte_in_row >> 6;
+  const int rr = (int)(r & 63), b = (int)(byte_in_row & 63);
+  return ((r >> 6) * nk + kt) * 4096 + rr * 64 + swz_chunk<16>(rr, b >> 4) * 16 + (b & 15);
 }
 
 // Digits of one element: q[0..S-1] from x and its row/column exponent.
@@ -103,7 +133,8 @@ __device__ __forceinline__ unsigned short to_bf16(float q) {
   return (unsigned short)(__float_as_uint(q) >> 16);
 }
 
-// INT8 digits (beta 6) are stored as two's-complement bytes (|q| <= 64).
+// INT8 digits (beta 7, one bit of headroom) are stored as two's-complement
+// bytes (|q| <= 64).
 // Small integer (|q| <= 16) to OCP FP8 E4M3 bits.
 __device__ __forceinline__ unsigned char to_e4m3(float qf) {
   int q = (int)qf;
@@ -130,15 +161,18 @@ __global__ void __launch_bounds__(256) split_digits_left(const SplitArgs a, cons
     const double x = (r < a.rows && c < a.cols) ? operand_value(a, r * a.ld + c) : 0.0;
     digits<S>(x, e, a.beta, q[t]);
   }
+  constexpr int ES = ET == 0 ? 2 : 1;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int64_t o = (int64_t)s * a.slice_stride + r * a.kp + kk0;
+    // element offset (row-major digits) or byte offset (tiled digits)
+    const int64_t o = a.tiled ? (int64_t)s * a.slice_stride * ES + slice_tile_offset(r, kk0 * ES, a.kp * ES)
+                              : ((int64_t)s * a.slice_stride + r * a.kp + kk0) * ES;
     if constexpr (ET == 0) {
       i4v v;
 #pragma unroll
       for (int t = 0; t < 4; ++t)
         v[t] = (int)to_bf16(q[2 * t][s]) | ((int)to_bf16(q[2 * t + 1][s]) << 16);
-      *reinterpret_cast<i4v*>(static_cast<unsigned short*>(out) + o) = v;
+      *reinterpret_cast<i4v*>(static_cast<unsigned char*>(out) + o) = v;
     } else if constexpr (ET == 2) {
       i2v v;
 #pragma unroll
@@ -193,9 +227,9 @@ __global__ void __launch_bounds__(256) split_digits_right(const SplitArgs a, con
     const int rem = w % (64 * PIECES);
     const int cc = rem / PIECES, p = rem % PIECES;
     const i4v v = *reinterpret_cast<const i4v*>(&tile[s][cc][p * 16]);
-    unsigned char* dst = static_cast<unsigned char*>(out) +
-                         ((int64_t)s * a.slice_stride + (c0 + cc) * a.kp + k0) * ES + p * 16;
-    *reinterpret_cast<i4v*>(dst) = v;
+    const int64_t o = a.tiled ? slice_tile_offset(c0 + cc, k0 * ES + p * 16, a.kp * ES)
+                              : ((c0 + cc) * a.kp + k0) * ES + p * 16;
+    *reinterpret_cast<i4v*>(static_cast<unsigned char*>(out) + (int64_t)s * a.slice_stride * ES + o) = v;
   }
 }
 
@@ -232,7 +266,7 @@ struct SliceTraits<1> {  // OCP FP8 E4M3 digits, v_mfma_f32_16x16x32_fp8_fp8
 };
 template <>
 struct SliceTraits<2> {  // INT8 digits, v_mfma_i32_16x16x64_i8 (exact int32 sums)
-  static constexpr int ES = 1, KSTEP = 64, CH = 16, BETA = 6;
+  static constexpr int ES = 1, KSTEP = 64, CH = 16, BETA = 7;
   typedef i4v frag_t;
   typedef i4v acc_t;
   __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
@@ -242,7 +276,47 @@ struct SliceTraits<2> {  // INT8 digits, v_mfma_i32_16x16x64_i8 (exact int32 sum
 
 constexpr double pow2neg(int e) { return 1.0 / (double)(1ull << e); }
 
-template <int ET, int S, int WM, int MI, int CACHE_B, int NSTAGE, int WPE>
+// Output of one wave tile (16 MI x 16 NI at rows r0.., columns c0..):
+// exponent scaling, then coef * T into every target block.
+template <int MI, int NI>
+__device__ __forceinline__ void store_tile(const SliceGemmArgs& g, const d4s (&acc)[MI][NI], int64_t r0, int64_t c0,
+                                           int fr, int fg) {
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + i * 16 + 4 * fg + v;
+        const int64_t c = c0 + j * 16 + fr;
+        if (r >= g.m || c >= g.n) continue;
+        const int ea = g.ea[r], eb = g.eb[c];
+        const double t = (ea == INT_MIN || eb == INT_MIN) ? 0.0 : ldexp(acc[i][j][v], ea + eb);
+        const int64_t off = r * g.ldc + c;
+        for (int q = 0; q < g.ntgt; ++q) {
+          double val = g.coef[q] * t;
+          if (g.mode[q] == TGT_ACCUM) val += g.c[q][off];
+          g.c[q][off] = val;
+        }
+      }
+}
+
+
+
+// Block -> output tile, XCD-aware and grouped by 8 tile rows (as in the
+// FP64 GEMM): consecutive block ids land on different XCDs, so each XCD
+// gets a contiguous run of tiles.
+__device__ __forceinline__ void slice_tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int T = tiles_m * tiles_n, w = blockIdx.x;
+  const int x = w % 8, slot = w / 8, base = T / 8, rem = T % 8;
+  const int t = x * base + (x < rem ? x : rem) + slot;
+  const int per_group = 8 * tiles_n, group = t / per_group, first_m = group * 8;
+  const int gm = min(tiles_m - first_m, 8), in_g = t - group * per_group;
+  tm = first_m + in_g % gm;
+  tn = in_g / gm;
+}
+
+template <int ET, int S, int WM, int MI, int CACHE_B, int NSTAGE, int WPE, int PERSIST>
 __global__ void __launch_bounds__(WM * 2 * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 slice_gemm(const SliceGemmArgs g) {
   typedef SliceTraits<ET> Tr;
@@ -268,25 +342,14 @@ slice_gemm(const SliceGemmArgs g) {
   const int tiles_n = (int)((g.n + BN - 1) / BN);
   // XCD-aware grouped tile order (as in the FP64 GEMM).
   int tm, tn;
-  {
-    const int T = tiles_m * tiles_n, w = blockIdx.x;
-    const int x = w % 8, slot = w / 8, base = T / 8, rem = T % 8;
-    const int t = x * base + (x < rem ? x : rem) + slot;
-    const int per_group = 8 * tiles_n, group = t / per_group, first_m = group * 8;
-    const int gm = min(tiles_m - first_m, 8), in_g = t - group * per_group;
-    tm = first_m + in_g % gm;
-    tn = in_g / gm;
-  }
+  slice_tile_coords(tiles_m, tiles_n, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 16 * MI, wn0 = (wave & 1) * 32;
   const int fr = lane & 15, fg = lane >> 4;
 
   // Byte offset of chunk ch of row r (swizzled).
-  auto swz = [](int r, int ch) {
-    if constexpr (CH == 16) return r * ROWB + ((ch ^ ((r >> 2) & 3)) * CH);
-    else return r * ROWB + ((ch ^ ((r >> 3) & 3)) * CH);
-  };
+  auto swz = [](int r, int ch) { return r * ROWB + swz_chunk<CH>(r, ch) * CH; };
 
   // Global -> LDS staging.  Piece v = tid + i NT of a k-step covers 16 bytes
   // of row r of slice s.  With PPR pieces per row and NT a multiple of PPR
@@ -305,15 +368,10 @@ slice_gemm(const SliceGemmArgs g) {
   const int64_t ga_lane = g_lane(BM, g.slice_stride_a);
   const int64_t gb_lane = g_lane(BN, g.slice_stride_b);
   // LDS position of (linear row lr, piece lp); the swizzle depends only on
-  // row bits 2..4, which whole-pass and whole-slice offsets leave unchanged.
-  const int l_lane_a = [&] {
-    if constexpr (CH == 16) return lr * ROWB + ((lp ^ ((lr >> 2) & 3)) * CH);
-    else return lr * ROWB + (((2 * lp) ^ ((lr >> 3) & 3)) * CH);
-  }();
-  const int l_lane_a2 = [&] {  // second 8-byte half (FP8 only)
-    if constexpr (CH == 16) return 0;
-    else return lr * ROWB + (((2 * lp + 1) ^ ((lr >> 3) & 3)) * CH);
-  }();
+  // row bits 1..3, which whole-pass and whole-slice offsets (multiples of 16
+  // rows) leave unchanged.
+  const int l_lane_a = CH == 16 ? swz(lr, lp) : swz(lr, 2 * lp);
+  const int l_lane_a2 = CH == 16 ? 0 : swz(lr, 2 * lp + 1);  // second 8-byte half (FP8 only)
   const unsigned char* ga = static_cast<const unsigned char*>(g.a) + m0 * g.kp * ES;
   const unsigned char* gb = static_cast<const unsigned char*>(g.b) + n0 * g.kp * ES;
   i4v ra[A_LD], rb[B_LD];
@@ -326,7 +384,7 @@ slice_gemm(const SliceGemmArgs g) {
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
-      if (i * NT + tid < A_LD_TOTAL) {
+      if (A_LD_TOTAL % NT == 0 || i * NT + tid < A_LD_TOTAL) {
         int s, r0;
         pass_of(i, BM, s, r0);
         const unsigned char* base = ga + (s * g.slice_stride_a + (int64_t)r0 * g.kp + k0) * ES;
@@ -335,7 +393,7 @@ slice_gemm(const SliceGemmArgs g) {
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
-      if (i * NT + tid < B_LD_TOTAL) {
+      if (B_LD_TOTAL % NT == 0 || i * NT + tid < B_LD_TOTAL) {
         int s, r0;
         pass_of(i, BN, s, r0);
         const unsigned char* base = gb + (s * g.slice_stride_b + (int64_t)r0 * g.kp + k0) * ES;
@@ -355,7 +413,7 @@ slice_gemm(const SliceGemmArgs g) {
     unsigned char* base = lds + st * STAGE;
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
-      if (i * NT + tid < A_LD_TOTAL) {
+      if (A_LD_TOTAL % NT == 0 || i * NT + tid < A_LD_TOTAL) {
         int s, r0;
         pass_of(i, BM, s, r0);
         put(base + s * BM * ROWB + r0 * ROWB, ra[i]);
@@ -363,7 +421,7 @@ slice_gemm(const SliceGemmArgs g) {
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
-      if (i * NT + tid < B_LD_TOTAL) {
+      if (B_LD_TOTAL % NT == 0 || i * NT + tid < B_LD_TOTAL) {
         int s, r0;
         pass_of(i, BN, s, r0);
         put(base + A_BYTES + s * BN * ROWB + r0 * ROWB, rb[i]);
@@ -377,6 +435,16 @@ slice_gemm(const SliceGemmArgs g) {
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = d4s{0.0, 0.0, 0.0, 0.0};
 
+  // Level sums (PERSIST): level d = s + t in lvl[d - 2].
+  acc_t lvl[PERSIST ? S : 1][MI][NI];
+#pragma unroll
+  for (int d = 0; d < (PERSIST ? S : 1); ++d)
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) lvl[d][i][j] = acc_t{0, 0, 0, 0};
+  int since = 0;
+
   const int64_t nk = g.kp / BK;
   gload(0);
   lstore(0);
@@ -385,78 +453,246 @@ slice_gemm(const SliceGemmArgs g) {
     const int st = NSTAGE == 2 ? (int)(kt & 1) : 0;
     if (kt + 1 < nk) gload((kt + 1) * BK);
     const unsigned char* base = lds + st * STAGE;
-    frag_t fa[S][MI];
-    frag_t fbc[CACHE_B ? S : 1][NI];
+    if constexpr (PERSIST) {
+      // Every B fragment of the k-step stays in registers; the A fragments
+      // of one slice at a time.  Level sums live across k-steps.
+      frag_t fbc[S][NI];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-        fa[s][i] = *reinterpret_cast<const frag_t*>(base + s * BM * ROWB + swz(wm0 + i * 16 + fr, fg));
-      if constexpr (CACHE_B) {
+      for (int t = 0; t < S; ++t)
 #pragma unroll
         for (int j = 0; j < NI; ++j)
-          fbc[s][j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + s * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
-      }
-    }
+          fbc[t][j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + t * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
 #pragma unroll
-    for (int d = 2; d <= S + 1; ++d) {
-      // Keep each level's fragment reads and accumulators within the level:
-      // hoisting them across levels costs more registers than it hides.
-      __builtin_amdgcn_sched_barrier(0);
-      acc_t lv[MI][NI];
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int j = 0; j < NI; ++j) lv[i][j] = acc_t{0, 0, 0, 0};
-#pragma unroll
-      for (int s = 1; s < d; ++s) {
-        const int t = d - s;
-        if (s > S || t > S) continue;
-        frag_t fb[NI];
-#pragma unroll
-        for (int j = 0; j < NI; ++j) {
-          if constexpr (CACHE_B)
-            fb[j] = fbc[t - 1][j];
-          else
-            fb[j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + (t - 1) * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
-        }
+      for (int s = 1; s <= S; ++s) {
+        frag_t fa[MI];
 #pragma unroll
         for (int i = 0; i < MI; ++i)
+          fa[i] = *reinterpret_cast<const frag_t*>(base + (s - 1) * BM * ROWB + swz(wm0 + i * 16 + fr, fg));
 #pragma unroll
-          for (int j = 0; j < NI; ++j) lv[i][j] = Tr::mfma(fa[s - 1][i], fb[j], lv[i][j]);
+        for (int t = 1; t <= S + 1 - s; ++t)
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j) lvl[s + t - 2][i][j] = Tr::mfma(fa[i], fbc[t - 1][j], lvl[s + t - 2][i][j]);
       }
-      const double sc = pow2neg(BETA * d);
+      if (++since == g.kflush || kt + 1 == nk) {
+        since = 0;
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
+        for (int d = 2; d <= S + 1; ++d) {
+          const double sc = pow2neg(BETA * d);
 #pragma unroll
-        for (int j = 0; j < NI; ++j)
+          for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[i][j][v] = __builtin_fma((double)lv[i][j][v], sc, acc[i][j][v]);
+            for (int j = 0; j < NI; ++j) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                acc[i][j][v] = __builtin_fma((double)lvl[d - 2][i][j][v], sc, acc[i][j][v]);
+              lvl[d - 2][i][j] = acc_t{0, 0, 0, 0};
+            }
+        }
+      }
+    } else {
+      frag_t fa[S][MI];
+      frag_t fbc[CACHE_B ? S : 1][NI];
+  #pragma unroll
+      for (int s = 0; s < S; ++s) {
+  #pragma unroll
+        for (int i = 0; i < MI; ++i)
+          fa[s][i] = *reinterpret_cast<const frag_t*>(base + s * BM * ROWB + swz(wm0 + i * 16 + fr, fg));
+        if constexpr (CACHE_B) {
+  #pragma unroll
+          for (int j = 0; j < NI; ++j)
+            fbc[s][j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + s * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
+        }
+      }
+      // Levels d = 2 .. S+1.  The MFMAs of level d are issued while the sums of
+      // level d-1 are flushed into FP64 (two accumulator sets), so the flush's
+      // VALU work overlaps the matrix pipe; scheduling barriers between levels
+      // keep register use bounded.
+      acc_t lv[2][MI][NI];
+      auto flush = [&](const acc_t (&x)[MI][NI], int d) {
+        const double sc = pow2neg(BETA * d);
+  #pragma unroll
+        for (int i = 0; i < MI; ++i)
+  #pragma unroll
+          for (int j = 0; j < NI; ++j)
+  #pragma unroll
+            for (int v = 0; v < 4; ++v) acc[i][j][v] = __builtin_fma((double)x[i][j][v], sc, acc[i][j][v]);
+      };
+  #pragma unroll
+      for (int d = 2; d <= S + 1; ++d) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int cur = d & 1;
+  #pragma unroll
+        for (int i = 0; i < MI; ++i)
+  #pragma unroll
+          for (int j = 0; j < NI; ++j) lv[cur][i][j] = acc_t{0, 0, 0, 0};
+  #pragma unroll
+        for (int s = 1; s < d; ++s) {
+          const int t = d - s;
+          if (s > S || t > S) continue;
+          frag_t fb[NI];
+  #pragma unroll
+          for (int j = 0; j < NI; ++j) {
+            if constexpr (CACHE_B)
+              fb[j] = fbc[t - 1][j];
+            else
+              fb[j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + (t - 1) * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
+          }
+  #pragma unroll
+          for (int i = 0; i < MI; ++i)
+  #pragma unroll
+            for (int j = 0; j < NI; ++j) lv[cur][i][j] = Tr::mfma(fa[s - 1][i], fb[j], lv[cur][i][j]);
+        }
+        if (d > 2) flush(lv[cur ^ 1], d - 1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      flush(lv[(S + 1) & 1], S + 1);
     }
     if (NSTAGE == 1) __syncthreads();
     if (kt + 1 < nk) lstore(NSTAGE == 2 ? (st ^ 1) : 0);
     __syncthreads();
   }
 
-  // Epilogue: exponent scaling, then coef * T into every target block.
+  store_tile<MI, NI>(g, acc, m0 + wm0, n0 + wn0, fr, fg);
+}
+
+// ---------------------------------------------------------------------------
+// Slice GEMM with direct global -> LDS loads (BF16 and INT8 digits: rows of
+// 64 bytes in 16-byte chunks, digits in the tiled layout).  64 x 64 block
+// tile, 4 waves of 32 x 32, one wave per SIMD.  Per k-step every thread
+// copies 16 bytes of each A and each B slice tile straight into LDS
+// (buffer_load_dwordx4 ... lds: lane l of a wave writes bytes 16 l .. 16 l +
+// 15 after the wave's LDS base); the tiles are stored in LDS order, so the
+// copy is contiguous on both sides.  Two LDS stages: the loads of k-step kt + 1 are issued
+// during the MFMAs of k-step kt, one after each slice pair until all are
+// out.  Pairs run level by level (d = s + t = 2 .. S + 1); level d needs
+// only the new fragments of slice d - 1, read from LDS one level ahead.
+// Level sums stay in registers across k-steps and go to FP64 every
+// g.kflush k-steps.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+template <int ET, int S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+slice_gemm_dma(const SliceGemmArgs g) {
+  typedef SliceTraits<ET> Tr;
+  typedef typename Tr::frag_t frag_t;
+  typedef typename Tr::acc_t acc_t;
+  constexpr int ES = Tr::ES, BK = Tr::KSTEP, BETA = Tr::BETA;
+  static_assert(Tr::CH == 16 && BK * ES == 64, "rows of four 16-byte chunks");
+  constexpr int BM = 64, BN = 64, ROWB = 64, MI = 2, NI = 2;
+  constexpr int SLICE = BM * ROWB;  // 4 KB per slice tile (A and B alike)
+  constexpr int A_BYTES = S * SLICE;
+  constexpr int STAGE = 2 * A_BYTES;
+  static_assert(2 * STAGE <= 160 * 1024, "two stages must fit LDS");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+
+  const int tiles_m = (int)((g.m + BM - 1) / BM);
+  const int tiles_n = (int)((g.n + BN - 1) / BN);
+  int tm, tn;
+  slice_tile_coords(tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+  const int fr = lane & 15, fg = lane >> 4;
+
+  // Loads: the digits are tiled (slice_tile_offset), so the tile of slice s
+  // for k-step kt is 4 KB contiguous, already in LDS order; thread tid copies
+  // its bytes 16 tid .. 16 tid + 15.  Buffer loads with one resource per
+  // slice and block row (column) tile: its nk tiles, so any offset past them
+  // would read zeros rather than another tile.
+  const int64_t nk = g.kp / BK;
+  const unsigned char* ga = static_cast<const unsigned char*>(g.a) + (int64_t)tm * nk * 4096;
+  const unsigned char* gb = static_cast<const unsigned char*>(g.b) + (int64_t)tn * nk * 4096;
+  const int64_t sa = g.slice_stride_a * ES, sb = g.slice_stride_b * ES;
+  const int nrec = (int)(uint32_t)(nk * 4096);  // num_records is unsigned
+  const int voff = tid * 16;
+  const int wave_lds = wave * 64 * 16;
+  // Load number q (0 .. 2S-1) of k-step kt into stage st: A slice q / 2 or
+  // B slice q / 2.
+  auto dma = [&](int q, int64_t kt, int st) {
+    const int sl = q >> 1;
+    const unsigned char* base = (q & 1) ? gb + sl * sb : ga + sl * sa;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, nrec, 0x00020000);
+    unsigned char* dst = lds + st * STAGE + ((q & 1) ? A_BYTES : 0) + sl * SLICE + wave_lds;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_ptr)dst, 16, voff, (int)(kt * 4096), 0, 0);
+  };
+  auto frag = [&](const unsigned char* tile, int row) {
+    return *reinterpret_cast<const frag_t*>(tile + row * ROWB + swz_chunk<16>(row, fg) * 16);
+  };
+
+  d4s acc[MI][NI];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < NI; ++j)
+    for (int j = 0; j < NI; ++j) acc[i][j] = d4s{0.0, 0.0, 0.0, 0.0};
+
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = m0 + wm0 + i * 16 + 4 * fg + v;
-        const int64_t c = n0 + wn0 + j * 16 + fr;
-        if (r >= g.m || c >= g.n) continue;
-        const int ea = g.ea[r], eb = g.eb[c];
-        const double t = (ea == INT_MIN || eb == INT_MIN) ? 0.0 : ldexp(acc[i][j][v], ea + eb);
-        const int64_t off = r * g.ldc + c;
-        for (int q = 0; q < g.ntgt; ++q) {
-          double val = g.coef[q] * t;
-          if (g.mode[q] == TGT_ACCUM) val += g.c[q][off];
-          g.c[q][off] = val;
+  for (int q = 0; q < 2 * S; ++q) dma(q, 0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < nk; k0 += g.kflush) {
+    const int64_t k1 = min(nk, k0 + (int64_t)g.kflush);
+    acc_t lvl[S][MI][NI];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) lvl[d][i][j] = acc_t{0, 0, 0, 0};
+    for (int64_t kt = k0; kt < k1; ++kt) {
+      const int st = (int)(kt & 1);
+      // The last k-step reloads itself into the idle stage (never read), so
+      // the loads need no branch.
+      const int64_t knext = kt + 1 < nk ? kt + 1 : kt;
+      const unsigned char* ta = lds + st * STAGE;
+      const unsigned char* tb = ta + A_BYTES;
+      frag_t fa[S][MI], fb[S][NI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) fa[0][i] = frag(ta, wm0 + i * 16 + fr);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) fb[0][j] = frag(tb, wn0 + j * 16 + fr);
+      int q = 0;  // loads of the next k-step issued so far
+#pragma unroll
+      for (int d = 2; d <= S + 1; ++d) {
+        // Fragments of slice d (needed from level d + 1 on), one level ahead.
+        if (d <= S) {
+#pragma unroll
+          for (int i = 0; i < MI; ++i) fa[d - 1][i] = frag(ta + (d - 1) * SLICE, wm0 + i * 16 + fr);
+#pragma unroll
+          for (int j = 0; j < NI; ++j) fb[d - 1][j] = frag(tb + (d - 1) * SLICE, wn0 + j * 16 + fr);
+        }
+#pragma unroll
+        for (int s = 1; s < d; ++s) {
+          const int t = d - s;
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j)
+              lvl[d - 2][i][j] = Tr::mfma(fa[s - 1][i], fb[t - 1][j], lvl[d - 2][i][j]);
+          if (q < 2 * S) dma(q++, knext, st ^ 1);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
+#pragma unroll
+      for (; q < 2 * S; ++q) dma(q, knext, st ^ 1);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+#pragma unroll
+    for (int d = 2; d <= S + 1; ++d) {
+      const double sc = pow2neg(BETA * d);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] = __builtin_fma((double)lvl[d - 2][i][j][v], sc, acc[i][j][v]);
+    }
+  }
+
+  store_tile<MI, NI>(g, acc, m0 + wm0, n0 + wn0, fr, fg);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,37 +716,62 @@ static hipError_t launch_split_s(const SplitArgs& a, int* exps, void* out, hipSt
   return hipGetLastError();
 }
 
-// Two block shapes, both with 32 x 32 wave tiles:
+// Block shapes, all with 32 x 32 wave tiles:
 //   variant 0: 8 waves (128 x 64 outputs), 2 waves/SIMD, B fragments read
-//              from LDS for every slice pair;
+//              from LDS for every slice pair, levels flushed every k-step;
 //   variant 1: 4 waves (64 x 64 outputs), 1 wave/SIMD, every A and B
-//              fragment of the k-step cached in registers (half the LDS
-//              traffic, fewer waves to hide latency).
-// Default: variant 0 while it fits 256 registers without spilling.
+//              fragment of the k-step cached in registers, levels flushed
+//              every k-step;
+//   variant 2: as variant 1, with the level sums kept across k-steps and
+//              flushed to FP64 every slice_flush_steps k-steps;
+//   variant 3: slice_gemm_dma (BF16, INT8).
 template <int ET, int S, int V>
 static hipError_t launch_slice_v(const SliceGemmArgs& g, hipStream_t st) {
   typedef SliceTraits<ET> Tr;
-  constexpr int WM = V == 0 ? 4 : 2, CACHE_B = V == 0 ? 0 : 1, WPE = V == 0 ? 2 : 1;
+  constexpr int WM = V == 0 ? 4 : 2, CACHE_B = V == 0 ? 0 : 1, WPE = V == 0 ? 2 : 1, PERSIST = V == 2 ? 1 : 0;
   constexpr int BM = 32 * WM;
   constexpr int STAGE = S * (BM + 64) * Tr::KSTEP * Tr::ES;
   constexpr int NSTAGE = 2 * STAGE <= 160 * 1024 ? 2 : 1;
   static_assert(STAGE <= 160 * 1024, "slice tile does not fit LDS");
   const int64_t tiles = ((g.m + BM - 1) / BM) * ((g.n + 63) / 64);
   if (tiles <= 0) return hipSuccess;
-  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((slice_gemm<ET, S, WM, 2, CACHE_B, NSTAGE, WPE>), dim3((unsigned)tiles), dim3(WM * 2 * 64),
-                     0, st, g);
+  if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((slice_gemm<ET, S, WM, 2, CACHE_B, NSTAGE, WPE, PERSIST>), dim3((unsigned)tiles),
+                     dim3(WM * 2 * 64), 0, st, g);
   return hipGetLastError();
 }
 
-int default_slice_variant(int et, int S) { return (et == 1 ? S <= 8 : S <= 6) ? 0 : 1; }
+// Default: the direct-to-LDS shape for BF16 and INT8 digits; for FP8 the
+// 8-wave shape while it fits 256 registers, then the persistent-level one.
+int default_slice_variant(int et, int S) { return et != 1 ? 3 : (S <= 8 ? 0 : 2); }
+
+int resolve_slice_variant(int et, int S, int variant) {
+  if (variant < 0 || variant > 3) return default_slice_variant(et, S);
+  if (variant == 3 && et == 1) return default_slice_variant(et, S);
+  if (variant == 0 && S > (et == 1 ? 8 : 6)) return default_slice_variant(et, S);
+  return variant;
+}
+
+bool slice_variant_tiled(int variant) { return variant == 3; }
 
 template <int ET, int S>
 static hipError_t launch_slice_s(const SliceGemmArgs& g, int variant, hipStream_t st) {
-  if (variant < 0) variant = default_slice_variant(ET, S);
+  variant = resolve_slice_variant(ET, S, variant);
   if (variant == 0) {
     if constexpr (ET == 1 ? S <= 8 : S <= 6) return launch_slice_v<ET, S, 0>(g, st);
     else return hipErrorInvalidValue;
+  }
+  if (variant == 2) return launch_slice_v<ET, S, 2>(g, st);
+  if (variant == 3) {
+    if constexpr (ET != 1) {
+      const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
+      if (tiles <= 0) return hipSuccess;
+      if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((slice_gemm_dma<ET, S>), dim3((unsigned)tiles), dim3(256), 0, st, g);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   return launch_slice_v<ET, S, 1>(g, st);
 }
@@ -521,7 +782,26 @@ int slice_block_rows(int et, int S) {
   return 128;  // digit rows are padded to 128, a multiple of both shapes
 }
 
-int slice_kstep(int et) { return et == 2 ? 64 : 32; }
+int slice_kstep(int et) {
+  return et == 0 ? SliceTraits<0>::KSTEP : (et == 1 ? SliceTraits<1>::KSTEP : SliceTraits<2>::KSTEP);
+}
+int slice_beta(int et) {
+  return et == 0 ? SliceTraits<0>::BETA : (et == 1 ? SliceTraits<1>::BETA : SliceTraits<2>::BETA);
+}
+int slice_head(int et) { return et == 2 ? 1 : 0; }
+
+// Level sums stay exact while every partial sum is an integer below 2^24
+// (FP32) or 2^31 (int32).  Digit bounds: |q_1| <= 2^{b-h}, |q_s| <= 2^{b-1};
+// a level d = s + t has at most d - 1 pairs, two of them with a leading
+// digit, so per k element |level| <= 2^{2b-2} max(4, d + 1) <= 2^{2b-2} (S + 3).
+int slice_flush_steps(int et, int S) {
+  const int b = slice_beta(et);
+  const double per_k = std::ldexp(1.0, 2 * b - 2) * (S + 3);
+  const double lim = et == 2 ? 2147483647.0 : 16777216.0;
+  const int64_t kmax = (int64_t)(lim / per_k);
+  const int64_t steps = kmax / slice_kstep(et);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(steps, 1 << 20));
+}
 
 #define BQ_SPLIT_CASES(ET, X) \
   X(ET, 1) X(ET, 2) X(ET, 3) X(ET, 4) X(ET, 5) X(ET, 6) X(ET, 7) X(ET, 8)

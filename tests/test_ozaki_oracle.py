@@ -16,11 +16,11 @@ def test_reconstruction(kind, S, dist):
     """x = 2^e (sum_s q_s 2^-bs + rem) exactly, |rem| <= 2^(-bS-1); numpy's
     uniform draws are multiples of 2^-52, so S * beta >= 53 digits hold them
     with no remainder at all."""
-    beta = ozaki.BETA[kind]
+    beta, head = ozaki.BETA[kind], ozaki.HEAD[kind]
     rng = np.random.default_rng(5)
     X = inputs.blocks(rng, 20, 33, dist)[0]
     for axis in (1, 0):
-        Q, e, rem = ozaki.digits(X, beta, S, axis)
+        Q, e, rem = ozaki.digits(X, beta, S, axis, head)
         ee = e[:, None] if axis == 1 else e[None, :]
         rec = sum(np.ldexp(Q[s].astype(np.float64), -beta * (s + 1)) for s in range(S))
         assert np.array_equal(np.ldexp(rec + rem, ee), X)
@@ -31,17 +31,33 @@ def test_reconstruction(kind, S, dist):
 
 @pytest.mark.parametrize("kind,S", [("bf16", 6), ("fp8", 11), ("int8", 7)])
 def test_digit_bounds(kind, S):
-    beta = ozaki.BETA[kind]
+    beta, head = ozaki.BETA[kind], ozaki.HEAD[kind]
     rng = np.random.default_rng(6)
     X = inputs.blocks(rng, 40, 50, "logspread")[0]
-    Q, e, rem = ozaki.digits(X, beta, S, 1)
-    assert np.max(np.abs(Q[0])) <= 2 ** beta
+    # rows whose largest entry sits just below a power of two: the leading
+    # digit reaches its bound 2^(beta - head)
+    X[0] *= 0.5 / np.max(np.abs(X[0]))
+    X[0, 3] = 1.0 - 2.0 ** -12
+    X[1] *= 0.25 / np.max(np.abs(X[1]))
+    X[1, 7] = -(0.5 - 2.0 ** -20)
+    Q, e, rem = ozaki.digits(X, beta, S, 1, head)
+    assert np.max(np.abs(Q[0])) == 2 ** (beta - head)
     for s in range(1, S):
         assert np.max(np.abs(Q[s])) <= 2 ** (beta - 1)
     assert np.max(np.abs(rem)) <= 2.0 ** (-beta * S - 1)
     # the digit types hold these integers exactly
     lim = {"bf16": 256, "fp8": 16, "int8": 127}[kind]
     assert max(np.max(np.abs(q)) for q in Q) <= lim
+
+
+def test_int8_needs_headroom():
+    """Without the headroom bit a leading INT8 digit of beta 7 can be 128,
+    which a signed byte cannot hold; with it every digit fits."""
+    X = np.array([[1.0 - 2.0 ** -12, 0.25], [-0.75, 0.125]])
+    Q0, _, _ = ozaki.digits(X, 7, 3, 1, head=0)
+    assert np.max(np.abs(Q0[0])) == 128
+    Q1, _, _ = ozaki.digits(X, 7, 3, 1, head=ozaki.HEAD["int8"])
+    assert max(np.max(np.abs(q)) for q in Q1) <= 127
 
 
 @pytest.mark.parametrize("kind,S", [("bf16", 3), ("fp8", 5), ("int8", 3)])
