@@ -270,7 +270,7 @@ def main():
         # sampled result agrees with the FP64 result (itself ~1e-14 from the
         # oracle) to 5e-13; the error reported is then the oracle's.
         max_s = {"split_bf16": 8, "split_fp8": 14, "split_int8": 9}
-        start_s = {"split_bf16": 7, "split_fp8": 13, "split_int8": 8}
+        start_s = {"split_bf16": 7, "split_fp8": 13, "split_int8": 7}
         for prec in [x for x in args.split.split(",") if x]:
             tried = []
             S = start_s[prec]

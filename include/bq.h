@@ -50,7 +50,11 @@ typedef enum {
 
 /* op(X): N = as stored, T = biquaternion transpose, C = complex conjugate,
  * H = Hermitian conjugate (Sec. III, sign rules for T, *, dagger).
- * This build implements N and C; T and H return BQ_ERR_UNSUPPORTED. */
+ * For T and H the stored matrix is the transpose: op(A) is m x k when A is
+ * stored k x m (A.rows = k, A.cols = m), op(B) is k x n when B is stored
+ * n x k.  T and H read the transposed tiles straight from the stored layout
+ * (no copy); the sign rules are folded into the pre-combination and the
+ * combination weights. */
 typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
 
 /* Arithmetic of the real GEMMs.  FP64: FP64 MFMA.  The split forms (an
@@ -103,7 +107,8 @@ const char* bq_last_error_detail(void);
 /* Workspace for bq_gemm.  *resident_bytes lets every pre-combined operand
  * stay in memory at once; *min_bytes is the least the streamed plan needs
  * (pre-combinations formed one product at a time).  Either output pointer
- * may be NULL.  maskA/maskB as in BQ_MASK_*; op as in bq_gemm. */
+ * may be NULL.  maskA/maskB as in BQ_MASK_*.  m, n, k are the shapes of
+ * op(A) (m x k) and op(B) (k x n); the sizes hold for every op. */
 bq_status_t bq_gemm_workspace_size(int64_t m, int64_t n, int64_t k,
                                    unsigned maskA, unsigned maskB,
                                    bq_prec_t prec, int slices,

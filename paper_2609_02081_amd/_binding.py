@@ -176,7 +176,9 @@ def bq_gemm(A, B, C=None, *, opA="N", opB="N", mask_a=FULL, mask_b=FULL, prec="f
 
     Am = matrix(A, mask_a)
     Bm = matrix(B, mask_b)
-    m, k, n = Am.rows, Am.cols, Bm.cols
+    # op T and H take the stored matrix transposed
+    m, k = (Am.cols, Am.rows) if opA in ("T", "H") else (Am.rows, Am.cols)
+    n = Bm.rows if opB in ("T", "H") else Bm.cols
     dev = (A if _is_tensor(A) else next(t for t in A if t is not None)).device
     if C is None:
         C = torch.empty((8, m, n), dtype=torch.float64, device=dev)

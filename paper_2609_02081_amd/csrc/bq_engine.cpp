@@ -60,9 +60,19 @@ constexpr double kHad[4][4] = {{1, 1, 1, 1}, {1, 1, -1, -1}, {1, -1, 1, -1}, {1,
 // Q_w += kHadOut[w] * 1/4 * sum_q kHad[w][q] P_{5+q}
 constexpr double kHadOut[4] = {-0.25, 0.25, 0.25, 0.25};
 
-// Complex conjugation of an operand (Sec. III, sign rule for *): the unit
-// coefficient M_u becomes sgn[u] * conj(M_u).
-constexpr double kConjUnitSign[4] = {1.0, -1.0, 1.0, -1.0};
+// op(M) of an operand (Sec. III, sign rules for T, * and dagger): the unit
+// coefficient M_u (u = 1, i, j, k) becomes sgn[op][u] M_u, conjugated for *
+// and dagger, transposed for T and dagger.  In the component layout these
+// are the per-component signs (+,+,-,+ | +,+,-,+) for T, (+,-,+,- | -,+,-,+)
+// for * and (+,-,-,- | -,+,+,+) for dagger.
+constexpr double kOpUnitSign[4][4] = {
+    {1.0, 1.0, 1.0, 1.0},     // N
+    {1.0, 1.0, -1.0, 1.0},    // T
+    {1.0, -1.0, 1.0, -1.0},   // C (*)
+    {1.0, -1.0, -1.0, -1.0},  // H (dagger)
+};
+inline bool op_conj(bq_op_t o) { return o == BQ_OP_C || o == BQ_OP_H; }
+inline bool op_trans(bq_op_t o) { return o == BQ_OP_T || o == BQ_OP_H; }
 
 struct Cplx {
   double re, im;
@@ -88,6 +98,8 @@ struct Prod {
 };
 
 struct Plan {
+  int64_t m = 0, n = 0, k = 0;  // op(A) is m x k, op(B) k x n
+  bool ta = false, tb = false;  // A stored k x m, B stored n x k (op T or H)
   bool bilinear = false;
   std::vector<Prod> prods;
   bool combA_r = false, combA_i = false, combB_r = false, combB_i = false;
@@ -111,14 +123,14 @@ struct Problem {
   const double* a[8];
   const double* b[8];
   int64_t lda, ldb;
-  bool conjA, conjB;
+  bq_op_t opA, opB;
 };
 
 Plan make_plan(const Problem& P) {
-  const double sA = P.conjA ? -1.0 : 1.0;
-  const double sB = P.conjB ? -1.0 : 1.0;
-  auto usA = [&](int u) { return P.conjA ? kConjUnitSign[u] : 1.0; };
-  auto usB = [&](int u) { return P.conjB ? kConjUnitSign[u] : 1.0; };
+  const double sA = op_conj(P.opA) ? -1.0 : 1.0;
+  const double sB = op_conj(P.opB) ? -1.0 : 1.0;
+  auto usA = [&](int u) { return kOpUnitSign[P.opA][u]; };
+  auto usB = [&](int u) { return kOpUnitSign[P.opB][u]; };
 
   // Component-wise form: 16 complex products, absent ones skipped.
   Plan cw;
@@ -174,8 +186,20 @@ Plan make_plan(const Problem& P) {
   bl.combA_i = aI;
   bl.combB_r = bR;
   bl.combB_i = bI;
-  if (bl.real_gemms <= cw.real_gemms) return bl;
-  return cw;
+  Plan& best = bl.real_gemms <= cw.real_gemms ? bl : cw;
+  best.m = P.m;
+  best.n = P.n;
+  best.k = P.k;
+  best.ta = op_trans(P.opA);
+  best.tb = op_trans(P.opB);
+  return best;
+}
+
+// Workspace slot of one pre-combined operand: the stored orientation (op T
+// and H keep it), rows padded to whole 64-byte lines.  Sized for either
+// orientation, so the workspace query needs no op.
+size_t combo_slot_bytes(int64_t rows, int64_t cols) {
+  return std::max(size_t(rows) * size_t((cols + 7) / 8 * 8), size_t(cols) * size_t((rows + 7) / 8 * 8)) * 8;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -222,8 +246,8 @@ void workspace_need(const Plan& pl, const Prec& pr, int64_t m, int64_t n, int64_
   bool any = false;
   for (const Prod& p : pl.prods) any |= (p.L.combo >= 0);
   if (pl.bilinear && any) {
-    const size_t a1 = align256(size_t(m) * size_t(round_up(k, 8)) * 8);
-    const size_t b1 = align256(size_t(k) * size_t(round_up(n, 8)) * 8);
+    const size_t a1 = align256(combo_slot_bytes(m, k));
+    const size_t b1 = align256(combo_slot_bytes(k, n));
     const size_t per_q = (pl.combA_r + pl.combA_i) * a1 + (pl.combB_r + pl.combB_i) * b1;
     *resident = 4 * per_q;
     *minimum = per_q;
@@ -254,17 +278,17 @@ bq_status_t prec_of(bq_prec_t prec, int slices, Prec* out) {
 
 Problem problem_of(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B) {
   Problem P;
-  P.m = A->rows;
-  P.k = A->cols;
-  P.n = B->cols;
+  P.m = op_trans(opA) ? A->cols : A->rows;
+  P.k = op_trans(opA) ? A->rows : A->cols;
+  P.n = op_trans(opB) ? B->rows : B->cols;
   for (int c = 0; c < 8; ++c) {
     P.a[c] = A->comp[c];
     P.b[c] = B->comp[c];
   }
   P.lda = A->ld;
   P.ldb = B->ld;
-  P.conjA = (opA == BQ_OP_C);
-  P.conjB = (opB == BQ_OP_C);
+  P.opA = opA;
+  P.opB = opB;
   return P;
 }
 
@@ -309,18 +333,17 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
   for (int t = 0; t < 3; ++t)
     if (M[t]->ld > (int64_t(1) << 24))
       return fail(BQ_ERR_UNSUPPORTED, std::string(nm[t]) + ": ld above 2^24 elements is not supported");
-  if (A->cols != B->rows) return fail(BQ_ERR_INVALID_VALUE, "A.cols != B.rows");
-  if (C->rows != A->rows || C->cols != B->cols)
-    return fail(BQ_ERR_INVALID_VALUE, "C must be A.rows x B.cols");
+  // op(A) is m x k, op(B) is k x n.
+  const int64_t m = op_trans(opA) ? A->cols : A->rows, k = op_trans(opA) ? A->rows : A->cols;
+  const int64_t kb = op_trans(opB) ? B->cols : B->rows, n = op_trans(opB) ? B->rows : B->cols;
+  if (k != kb) return fail(BQ_ERR_INVALID_VALUE, "inner dimensions of op(A) and op(B) differ");
+  if (C->rows != m || C->cols != n) return fail(BQ_ERR_INVALID_VALUE, "C must be rows(op(A)) x cols(op(B))");
   if (C->rows > 0 && C->cols > 0)
     for (int c = 0; c < 8; ++c)
       if ((out_mask >> c & 1) && !C->comp[c])
         return fail(BQ_ERR_INVALID_VALUE, "output component " + std::to_string(c) + " is null");
-  if (opA == BQ_OP_T || opA == BQ_OP_H || opB == BQ_OP_T || opB == BQ_OP_H)
-    return fail(BQ_ERR_UNSUPPORTED, "op T and H are not implemented in this build");
   if (check_ws && ws_bytes > 0 && !ws) return fail(BQ_ERR_INVALID_VALUE, "ws is null but ws_bytes > 0");
 
-  const int64_t m = A->rows, n = B->cols, k = A->cols;
   Plan plan = make_plan(problem_of(opA, opB, A, B));
   size_t res = 0, mn = 0;
   workspace_need(plan, pr, m, n, k, &res, &mn);
@@ -338,8 +361,8 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
     std::vector<Range> ins;
     if (k > 0) {
       for (int c = 0; c < 8; ++c) {
-        if (A->comp[c]) ins.push_back(block_range(A->comp[c], m, k, A->ld));
-        if (B->comp[c]) ins.push_back(block_range(B->comp[c], k, n, B->ld));
+        if (A->comp[c]) ins.push_back(block_range(A->comp[c], A->rows, A->cols, A->ld));
+        if (B->comp[c]) ins.push_back(block_range(B->comp[c], B->rows, B->cols, B->ld));
       }
     }
     const size_t used_ws = use_stream ? mn : res;
@@ -435,16 +458,17 @@ struct Tracer {
 // Enqueue the plan.  Validation has passed.
 bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matrix_t* A, const bq_matrix_t* B,
                     bq_matrix_t* C, unsigned out_mask, void* ws, bool streamed, hipStream_t s) {
-  const int64_t m = A->rows, n = B->cols, k = A->cols;
+  const int64_t m = pl.m, n = pl.n, k = pl.k;
   if (m == 0 || n == 0) return BQ_OK;
   bool touched[8] = {};
   const int cfg_override = tile_override();
 
-  // Workspace slots for the pre-combined operands (rows padded to whole
-  // 64-byte lines so the GEMM takes its aligned 16-byte load path).
-  const int64_t kpad = round_up(k, 8), npad = round_up(n, 8);
-  const size_t a1 = align256(size_t(m) * size_t(kpad) * 8);
-  const size_t b1 = align256(size_t(k) * size_t(npad) * 8);
+  // Workspace slots for the pre-combined operands, in the operands' stored
+  // orientation (rows padded to whole 64-byte lines so the GEMM takes its
+  // aligned 16-byte load path).
+  const int64_t kpad = round_up(k, 8), npad = round_up(n, 8), mpad = round_up(m, 8);
+  const size_t a1 = align256(combo_slot_bytes(m, k));
+  const size_t b1 = align256(combo_slot_bytes(k, n));
   char* wp = static_cast<char*>(ws);
   double* cA_r[4] = {};
   double* cA_i[4] = {};
@@ -491,8 +515,18 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     if (sg.ntgt == 0) return hipSuccess;
     const int variant = bq::resolve_slice_variant(pr.et, pr.S, slice_variant());
     const int tiled = bq::slice_variant_tiled(variant) ? 1 : 0;
-    bq::SplitArgs xa{x1, x2, xw1, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp, sl.rows_pad * sl.kp, beta, head, 1, tiled};
-    bq::SplitArgs ya{y1, y2, yw1, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp, sl.cols_pad * sl.kp, beta, head, 0, tiled};
+    // The left factor takes one exponent per row of op(A): along the stored
+    // rows (row kernels) for N and C, along the stored columns (column
+    // kernels, which also transpose the digits) for T and H; the right factor
+    // the other way round.
+    bq::SplitArgs xa = pl.ta ? bq::SplitArgs{x1, x2, xw1, xw2, ldx, k, m, 0, sl.rows_pad, sl.kp,
+                                             sl.rows_pad * sl.kp, beta, head, 0, tiled}
+                             : bq::SplitArgs{x1, x2, xw1, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp,
+                                             sl.rows_pad * sl.kp, beta, head, 1, tiled};
+    bq::SplitArgs ya = pl.tb ? bq::SplitArgs{y1, y2, yw1, yw2, ldy, n, k, sl.cols_pad, 0, sl.kp,
+                                             sl.cols_pad * sl.kp, beta, head, 1, tiled}
+                             : bq::SplitArgs{y1, y2, yw1, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp,
+                                             sl.cols_pad * sl.kp, beta, head, 0, tiled};
     const double elems_x = double(m) * double(k), elems_y = double(k) * double(n);
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
@@ -532,9 +566,9 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     const bq_matrix_t* X = left ? A : B;
     for (int c = 0; c < 8; ++c) ca.src[c] = X->comp[c];
     ca.lds = X->ld;
-    ca.rows = left ? m : k;
-    ca.cols = left ? k : n;
-    ca.ldd = left ? kpad : npad;
+    ca.rows = X->rows;
+    ca.cols = X->cols;
+    ca.ldd = left ? (pl.ta ? mpad : kpad) : (pl.tb ? kpad : npad);
     ca.nq = nq;
     int nsrc = 0, ndst = 0;
     for (int c = 0; c < 8; ++c) nsrc += (ca.src[c] != nullptr);
@@ -569,10 +603,10 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       }
       L.r = L.r ? cA_r[slot] : nullptr;
       L.i = L.i ? cA_i[slot] : nullptr;
-      L.ld = kpad;
+      L.ld = pl.ta ? mpad : kpad;
       R.r = R.r ? cB_r[slot] : nullptr;
       R.i = R.i ? cB_i[slot] : nullptr;
-      R.ld = npad;
+      R.ld = pl.tb ? kpad : npad;
     }
     // Imaginary-only operands: (i s x) as a real operand x times i s.
     Cplx rot = {1.0, 0.0};
@@ -628,6 +662,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     g.lr = L.r; g.li = L.i; g.lda = L.ld;
     g.rr = R.r; g.ri = R.i; g.ldb = R.ld;
     g.m = m; g.n = n; g.k = k;
+    g.ta = pl.ta; g.tb = pl.tb;
     g.sL = L.s; g.sR = R.s;
     g.ldc = C->ld;
     g.ntgt = 0;
@@ -950,10 +985,10 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
     for (int pi = 0; pi < p->count; ++pi) {
       const bq_problem_t& q = p->probs[pi];
       const Plan& pl = p->plans[pi];
-      const int64_t m = q.A.rows, n = q.B.cols, k = q.A.cols;
+      const int64_t m = pl.m, n = pl.n, k = pl.k;  // op N or C: the stored shapes
       char* wp = static_cast<char*>(ws) + p->ws_off[pi];
       const int64_t kpad = round_up(k, 8), npad = round_up(n, 8);
-      const size_t a1 = align256(size_t(m) * size_t(kpad) * 8), b1 = align256(size_t(k) * size_t(npad) * 8);
+      const size_t a1 = align256(combo_slot_bytes(m, k)), b1 = align256(combo_slot_bytes(k, n));
       double *cAr[4], *cAi[4], *cBr[4], *cBi[4];
       for (int c = 0; c < 4; ++c) {
         cAr[c] = reinterpret_cast<double*>(wp); wp += a1;
@@ -1085,8 +1120,10 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
     bq_status_t st = validate(q.opA, q.opB, &q.A, &q.B, &q.C, prec, slices, nullptr, 0, 0xFFu, &pl, &streamed,
                               &dummy, false);
     if (st != BQ_OK) return fail(st, "problem " + std::to_string(i) + ": " + g_detail);
-    const int64_t m = q.A.rows, n = q.B.cols, k = q.A.cols;
+    const int64_t m = pl.m, n = pl.n, k = pl.k;
     if (pr.et < 0) {
+      if (op_trans(q.opA) || op_trans(q.opB))
+        return fail(BQ_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": FP64 batched plans take op N or C");
       for (int c = 0; c < 8; ++c)
         if (!q.A.comp[c] || !q.B.comp[c])
           return fail(BQ_ERR_UNSUPPORTED, "problem " + std::to_string(i) +
@@ -1108,8 +1145,8 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
       for (int c = 0; c < 8; ++c) {
         if (q.C.comp[c]) outs.push_back({block_range(q.C.comp[c], m, n, q.C.ld), i});
         if (k > 0) {
-          if (q.A.comp[c]) ins.push_back({block_range(q.A.comp[c], m, k, q.A.ld), i});
-          if (q.B.comp[c]) ins.push_back({block_range(q.B.comp[c], k, n, q.B.ld), i});
+          if (q.A.comp[c]) ins.push_back({block_range(q.A.comp[c], q.A.rows, q.A.cols, q.A.ld), i});
+          if (q.B.comp[c]) ins.push_back({block_range(q.B.comp[c], q.B.rows, q.B.cols, q.B.ld), i});
         }
       }
     }
@@ -1149,8 +1186,8 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
   p->order.resize(count);
   for (int i = 0; i < count; ++i) p->order[i] = i;
   auto work = [&](int i) {
-    const bq_problem_t& q = p->probs[i];
-    return double(q.A.rows) * double(q.B.cols) * double(q.A.cols);
+    const Plan& pl = p->plans[i];
+    return double(pl.m) * double(pl.n) * double(pl.k);
   };
   std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) { return work(a) > work(b); });
   p->blocks = 2 * std::max(1, h->cu_count);
@@ -1159,8 +1196,8 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
   key << h->arch << ":" << h->cu_count << ":" << pr.et << ":" << pr.S << ":";
   uint64_t hash = 1469598103934665603ull;
   for (int i : p->order) {
-    const bq_problem_t& q = p->probs[i];
-    const int64_t d[3] = {q.A.rows, q.B.cols, q.A.cols};
+    const Plan& pl = p->plans[i];
+    const int64_t d[3] = {pl.m, pl.n, pl.k};
     for (int64_t x : d) {
       hash ^= uint64_t(x);
       hash *= 1099511628211ull;

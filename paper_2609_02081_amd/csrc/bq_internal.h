@@ -46,6 +46,7 @@ struct GemmArgs {
   int64_t ldc;
   int xcd_remap;  // 1: deal contiguous tile ranges to the 8 XCDs
   int group_m;    // tile-rows per group of the grouped tile order (>= 1)
+  int ta, tb;     // 1: lr/li stored k x m (lda along m), rr/ri stored n x k (ldb along k)
 };
 
 // Linear combinations of quaternion components (the Hadamard rows of

@@ -68,13 +68,42 @@ struct TileSmem {
   static constexpr int PAD = 4;
   static constexpr int NA = (KIND == KIND_GAUSS || KIND == KIND_CR) ? 2 : 1;
   static constexpr int NB = (KIND == KIND_GAUSS || KIND == KIND_RC) ? 2 : 1;
-  double As[2][NA][BK][BM + PAD];
+  __attribute__((aligned(16))) double As[2][NA][BK][BM + PAD];
   __attribute__((aligned(16))) double Bs[2][NB][BK][BN + PAD];
 };
 
+// Stored operand tile: R rows of C contiguous elements (C even), moved in
+// pairs along the rows; pair v of thread tid + i NT is (row v / (C/2), column
+// 2 (v % (C/2))).  MODE 0: 16-byte loads; 1: 8-byte loads, no checks; 2:
+// checked against row_lim rows and col_lim columns (zeros outside).
+template <int MODE, int PAIRS, int C, int NT>
+__device__ __forceinline__ void load_pairs(double (&dst)[2 * PAIRS], const double* base, int64_t ld, int64_t row_lim,
+                                           int64_t col_lim, int tid) {
+#pragma unroll
+  for (int i = 0; i < PAIRS; ++i) {
+    const int v = tid + i * NT;
+    const int r = v / (C / 2), c = 2 * (v % (C / 2));
+    const uint32_t off = (uint32_t)(r * (uint32_t)ld + c);
+    if constexpr (MODE == 0) {
+      const d2 x = *reinterpret_cast<const d2*>(base + off);
+      dst[2 * i] = x[0];
+      dst[2 * i + 1] = x[1];
+    } else if constexpr (MODE == 1) {
+      dst[2 * i] = base[off];
+      dst[2 * i + 1] = base[off + 1];
+    } else {
+      const bool rok = r < row_lim;
+      dst[2 * i] = (rok && c < col_lim) ? base[off] : 0.0;
+      dst[2 * i + 1] = (rok && c + 1 < col_lim) ? base[off + 1] : 0.0;
+    }
+  }
+}
+
 // One output tile (m0, n0) of the complex product described by g: K loop and
 // epilogue.  Every thread of the block must call it (it synchronises).
-template <int KIND, int BM, int BN, int BK, int WM, int WN>
+// TA / TB: the left / right operand is stored transposed (op T or H: the
+// left one k x m, the right one n x k).
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
                                           TileSmem<KIND, BM, BN, BK>& sm) {
   constexpr int NWN = BN / WN;
@@ -89,11 +118,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   // Elements are moved in pairs along the contiguous dimension.
   constexpr int A_PAIRS = BM * BK / 2 / NT;
   constexpr int B_PAIRS = BK * BN / 2 / NT;
+  // Contiguous length of the stored tiles.
+  constexpr int AC = TA ? BM : BK;
+  constexpr int BC = TB ? BK : BN;
   static_assert(A_PAIRS * NT * 2 == BM * BK && B_PAIRS * NT * 2 == BK * BN, "tile / thread mismatch");
   static_assert(BK % 4 == 0 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
-  static_assert(((BN + PAD) * 8) % 16 == 0, "B rows must stay 16-byte aligned in LDS");
+  static_assert(((BN + PAD) * 8) % 16 == 0 && ((BM + PAD) * 8) % 16 == 0, "LDS rows must stay 16-byte aligned");
 
-  // Double-buffered LDS: the A tile k-major (As[k][i]), the B tile as stored.
+  // Double-buffered LDS, both tiles k-major: As[k][i], Bs[k][j].
   auto& As = sm.As;
   auto& Bs = sm.Bs;
 
@@ -106,8 +138,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   const int fk = lane >> 4;
 
   // Per-tile base pointers: all further offsets stay small (32-bit).
-  const double* pa[2] = {g.lr + m0 * g.lda, HAS_LI ? g.li + m0 * g.lda : nullptr};
-  const double* pb[2] = {g.rr + n0, HAS_RI ? g.ri + n0 : nullptr};
+  const int64_t a_off = TA ? m0 : m0 * g.lda;
+  const int64_t b_off = TB ? n0 * g.ldb : n0;
+  const double* pa[2] = {g.lr + a_off, HAS_LI ? g.li + a_off : nullptr};
+  const double* pb[2] = {g.rr + b_off, HAS_RI ? g.ri + b_off : nullptr};
   const int64_t mrem = g.m - m0;
   const int64_t nrem = g.n - n0;
   // Interior tiles load without bounds checks (16-byte loads when the rows
@@ -120,106 +154,63 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 
   auto gload = [&](int64_t k0) {
     const bool kfull = (k0 + BK <= g.k);
+    const int64_t kleft = g.k - k0;
+    // Stored tiles: A is BM x BK (TA: BK x BM) from k0, B is BK x BN (TB: BN x BK).
+    const int64_t a_step = TA ? k0 * g.lda : k0;
+    const int64_t b_step = TB ? k0 : k0 * g.ldb;
+    const int64_t a_rows = TA ? kleft : mrem, a_cols = TA ? mrem : kleft;
+    const int64_t b_rows = TB ? nrem : kleft, b_cols = TB ? kleft : nrem;
     if (fast && kfull) {
 #pragma unroll
-      for (int p = 0; p < NA; ++p) {
-        const double* base = pa[p] + k0;
+      for (int p = 0; p < NA; ++p) load_pairs<0, A_PAIRS, AC, NT>(ra[p], pa[p] + a_step, g.lda, 0, 0, tid);
 #pragma unroll
-        for (int i = 0; i < A_PAIRS; ++i) {
-          const int v = tid + i * NT;
-          const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
-          const d2 x = *reinterpret_cast<const d2*>(base + (uint32_t)(r * (uint32_t)g.lda + c));
-          ra[p][2 * i] = x[0];
-          ra[p][2 * i + 1] = x[1];
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < NB; ++p) {
-        const double* base = pb[p] + k0 * g.ldb;
-#pragma unroll
-        for (int i = 0; i < B_PAIRS; ++i) {
-          const int v = tid + i * NT;
-          const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
-          const d2 x = *reinterpret_cast<const d2*>(base + (uint32_t)(r * (uint32_t)g.ldb + c));
-          rb[p][2 * i] = x[0];
-          rb[p][2 * i + 1] = x[1];
-        }
-      }
+      for (int p = 0; p < NB; ++p) load_pairs<0, B_PAIRS, BC, NT>(rb[p], pb[p] + b_step, g.ldb, 0, 0, tid);
     } else if (interior && kfull) {
       // Interior tile whose rows are not 16-byte aligned: the same pattern
       // with 8-byte loads, still without bounds checks.
 #pragma unroll
-      for (int p = 0; p < NA; ++p) {
-        const double* base = pa[p] + k0;
+      for (int p = 0; p < NA; ++p) load_pairs<1, A_PAIRS, AC, NT>(ra[p], pa[p] + a_step, g.lda, 0, 0, tid);
 #pragma unroll
-        for (int i = 0; i < A_PAIRS; ++i) {
-          const int v = tid + i * NT;
-          const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
-          const uint32_t off = (uint32_t)(r * (uint32_t)g.lda + c);
-          ra[p][2 * i] = base[off];
-          ra[p][2 * i + 1] = base[off + 1];
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < NB; ++p) {
-        const double* base = pb[p] + k0 * g.ldb;
-#pragma unroll
-        for (int i = 0; i < B_PAIRS; ++i) {
-          const int v = tid + i * NT;
-          const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
-          const uint32_t off = (uint32_t)(r * (uint32_t)g.ldb + c);
-          rb[p][2 * i] = base[off];
-          rb[p][2 * i + 1] = base[off + 1];
-        }
-      }
+      for (int p = 0; p < NB; ++p) load_pairs<1, B_PAIRS, BC, NT>(rb[p], pb[p] + b_step, g.ldb, 0, 0, tid);
     } else {
-      const int64_t kleft = g.k - k0;
 #pragma unroll
-      for (int p = 0; p < NA; ++p) {
-        const double* base = pa[p] + k0;
+      for (int p = 0; p < NA; ++p)
+        load_pairs<2, A_PAIRS, AC, NT>(ra[p], pa[p] + a_step, g.lda, a_rows, a_cols, tid);
 #pragma unroll
-        for (int i = 0; i < A_PAIRS; ++i) {
-          const int v = tid + i * NT;
-          const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
-          const bool rok = r < mrem;
-          const uint32_t off = (uint32_t)(r * (uint32_t)g.lda + c);
-          ra[p][2 * i] = (rok && c < kleft) ? base[off] : 0.0;
-          ra[p][2 * i + 1] = (rok && c + 1 < kleft) ? base[off + 1] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < NB; ++p) {
-        const double* base = pb[p] + k0 * g.ldb;
-#pragma unroll
-        for (int i = 0; i < B_PAIRS; ++i) {
-          const int v = tid + i * NT;
-          const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
-          const bool kok = r < kleft;
-          const uint32_t off = (uint32_t)(r * (uint32_t)g.ldb + c);
-          rb[p][2 * i] = (kok && c < nrem) ? base[off] : 0.0;
-          rb[p][2 * i + 1] = (kok && c + 1 < nrem) ? base[off + 1] : 0.0;
-        }
-      }
+      for (int p = 0; p < NB; ++p)
+        load_pairs<2, B_PAIRS, BC, NT>(rb[p], pb[p] + b_step, g.ldb, b_rows, b_cols, tid);
     }
   };
+  // A stored m-major (N) is transposed on the way into LDS; stored k-major
+  // (TA) it goes in as is.  B the other way round.
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_PAIRS; ++i) {
       const int v = tid + i * NT;
-      const int r = v / (BK / 2), c = 2 * (v % (BK / 2));
+      const int r = v / (AC / 2), c = 2 * (v % (AC / 2));
 #pragma unroll
       for (int p = 0; p < NA; ++p) {
-        As[buf][p][c][r] = ra[p][2 * i];
-        As[buf][p][c + 1][r] = ra[p][2 * i + 1];
+        if constexpr (TA) {
+          *reinterpret_cast<d2*>(&As[buf][p][r][c]) = d2{ra[p][2 * i], ra[p][2 * i + 1]};
+        } else {
+          As[buf][p][c][r] = ra[p][2 * i];
+          As[buf][p][c + 1][r] = ra[p][2 * i + 1];
+        }
       }
     }
 #pragma unroll
     for (int i = 0; i < B_PAIRS; ++i) {
       const int v = tid + i * NT;
-      const int r = v / (BN / 2), c = 2 * (v % (BN / 2));
+      const int r = v / (BC / 2), c = 2 * (v % (BC / 2));
 #pragma unroll
-      for (int p = 0; p < NB; ++p)
-        *reinterpret_cast<d2*>(&Bs[buf][p][r][c]) = d2{rb[p][2 * i], rb[p][2 * i + 1]};
+      for (int p = 0; p < NB; ++p) {
+        if constexpr (TB) {
+          Bs[buf][p][c][r] = rb[p][2 * i];
+          Bs[buf][p][c + 1][r] = rb[p][2 * i + 1];
+        } else {
+          *reinterpret_cast<d2*>(&Bs[buf][p][r][c]) = d2{rb[p][2 * i], rb[p][2 * i + 1]};
+        }
+      }
     }
   };
 
@@ -330,7 +321,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
       }
 }
 
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE>
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0>
 __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 cgemm_f64(const GemmArgs g) {
@@ -339,7 +330,7 @@ cgemm_f64(const GemmArgs g) {
   const int tiles_n = (int)((g.n + BN - 1) / BN);
   int tm, tn;
   tile_coords(tiles_m, tiles_n, g.xcd_remap, g.group_m, tm, tn);
-  gemm_tile<KIND, BM, BN, BK, WM, WN>(g, (int64_t)tm * BM, (int64_t)tn * BN, sm);
+  gemm_tile<KIND, BM, BN, BK, WM, WN, TA, TB>(g, (int64_t)tm * BM, (int64_t)tn * BN, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,19 +497,25 @@ int default_tile_config(int kind, int64_t m, int64_t n, int64_t k) {
   return 0;
 }
 
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE>
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0>
 static hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
   const int64_t tm = (g.m + BM - 1) / BM, tn = (g.n + BN - 1) / BN;
   const int64_t tiles = tm * tn;
   if (tiles <= 0) return hipSuccess;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   constexpr int NT = (BM / WM) * (BN / WN) * 64;
-  hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE>), dim3((unsigned)tiles), dim3(NT), 0, s, g);
+  hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE, TA, TB>), dim3((unsigned)tiles), dim3(NT), 0, s, g);
   return hipGetLastError();
 }
 
 template <int KIND>
 static hipError_t launch_kind(const GemmArgs& g, int cfg, hipStream_t s) {
+  // Transposed operands (op T or H) run the default tile configuration.
+  if (g.ta || g.tb) {
+    if (g.ta && g.tb) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 1, 1>(g, s);
+    if (g.ta) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 1, 0>(g, s);
+    return launch_one<KIND, 64, 64, 16, 32, 32, 2, 0, 1>(g, s);
+  }
   switch (cfg) {
     case 0: return launch_one<KIND, 64, 64, 16, 32, 32, 2>(g, s);
     case 1: return launch_one<KIND, 64, 64, 16, 32, 32, 1>(g, s);

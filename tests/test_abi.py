@@ -92,11 +92,22 @@ def test_shapes_and_leading_dimensions():
     assert check(mis, mat(5, 3, 2 * FAKE), mat(4, 3, 3 * FAKE), ws=ws[0], ws_bytes=ws[1]) == INVALID
 
 
-def test_unsupported_ops_and_precisions():
+def test_ops_and_precisions():
     A, Bm, C = mat(4, 4, FAKE), mat(4, 4, 2 * FAKE), mat(4, 4, 3 * FAKE)
+    for op in (1, 2, 3):
+        assert check(A, Bm, C, opA=op, ws=4 * FAKE, ws_bytes=1 << 30) == OK
+        assert check(A, Bm, C, opB=op, ws=4 * FAKE, ws_bytes=1 << 30) == OK
+    # op T / H take the stored matrix transposed: op(A) 4 x 5 from A stored
+    # 5 x 4, op(B) 5 x 3 from B stored 3 x 5
+    ws = dict(ws=4 * FAKE, ws_bytes=1 << 30)
+    At, Bt = mat(5, 4, FAKE), mat(3, 5, 2 * FAKE)
+    Bn, C43 = mat(5, 3, 2 * FAKE), mat(4, 3, 3 * FAKE)
     for op in (1, 3):
-        assert check(A, Bm, C, opA=op, ws=4 * FAKE, ws_bytes=1 << 30) == UNSUPPORTED
-        assert check(A, Bm, C, opB=op, ws=4 * FAKE, ws_bytes=1 << 30) == UNSUPPORTED
+        assert check(At, Bn, C43, opA=op, **ws) == OK
+        assert check(mat(4, 5, FAKE), Bt, C43, opB=op, **ws) == OK
+        assert check(At, Bt, C43, opA=op, opB=op, **ws) == OK
+        assert check(At, Bn, C43, **ws) == INVALID          # N: A 5 x 4 does not chain with B 5 x 3
+        assert check(At, Bn, mat(5, 3, 3 * FAKE), opA=op, **ws) == INVALID  # C must be 4 x 3
     assert check(A, Bm, C, opA=7) == INVALID
     assert check(A, Bm, C, prec=9) == INVALID
     assert check(A, Bm, C, slices=-1) == INVALID
@@ -124,9 +135,10 @@ def test_alias_detection():
 def test_workspace_sizes_and_errors():
     m, n, k = 100, 60, 40
     res, mn = ws_need(m, n, k)
-    up8 = lambda x: (x + 7) // 8 * 8      # combination buffers: rows padded to 64 bytes
-    a1 = (m * up8(k) * 8 + 255) // 256 * 256
-    b1 = (k * up8(n) * 8 + 255) // 256 * 256
+    up8 = lambda x: (x + 7) // 8 * 8      # combination buffers: rows padded to 64 bytes,
+    slot = lambda r, c: max(r * up8(c), c * up8(r)) * 8   # in either orientation (op N or T)
+    a1 = (slot(m, k) + 255) // 256 * 256
+    b1 = (slot(k, n) + 255) // 256 * 256
     assert res == 4 * (2 * a1 + 2 * b1) and mn == 2 * a1 + 2 * b1
     rq_res, rq_min = ws_need(m, n, k, 0x0F, 0x0F)
     assert rq_res == 4 * (a1 + b1) and rq_min == a1 + b1

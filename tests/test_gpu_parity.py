@@ -66,11 +66,60 @@ def test_unit_blocks_bit_exact(bq):
             assert np.array_equal(run(bq, A, B), oracle.gemm(A, B)), (u, v)
 
 
-@pytest.mark.parametrize("opA,opB", [("C", "N"), ("N", "C"), ("C", "C")])
-def test_conjugate_ops(bq, opA, opB):
-    A, B = inputs.pair(96, 80, 72, "normal", seed=3)
-    ref = oracle.gemm(oracle.conj(A) if opA == "C" else A, oracle.conj(B) if opB == "C" else B)
+OP_FN = {"N": lambda M: M, "T": oracle.transpose, "C": oracle.conj, "H": oracle.herm}
+
+
+def stored_pair(m, k, n, opA, opB, dist, seed, **kw):
+    """Stored operands for op(A) (m x k) and op(B) (k x n): T and H store
+    the transpose (A k x m, B n x k)."""
+    rng = np.random.default_rng(seed)
+    A = inputs.blocks(rng, *((k, m) if opA in "TH" else (m, k)), dist, **kw)
+    B = inputs.blocks(rng, *((n, k) if opB in "TH" else (k, n)), dist, **kw)
+    return A, B
+
+
+@pytest.mark.parametrize("opA", ["N", "T", "C", "H"])
+@pytest.mark.parametrize("opB", ["N", "T", "C", "H"])
+def test_all_ops(bq, opA, opB):
+    """Every op pair (Sec. III sign rules for T, * and dagger), the oracle
+    applying its own op to the stored operands; ragged shape."""
+    A, B = stored_pair(96, 80, 72, opA, opB, "normal", seed=3)
+    print(f"ops {opA}{opB}", flush=True)
+    ref = oracle.gemm(OP_FN[opA](A), OP_FN[opB](B))
     assert oracle.rel_frobenius(run(bq, A, B, opA=opA, opB=opB), ref) <= TOL
+
+
+@pytest.mark.parametrize("opA,opB", [("T", "N"), ("N", "H"), ("H", "T")])
+def test_transposed_ops_integer_bit_exact(bq, opA, opB):
+    """Integer inputs through the transposed loads: bit-exact; odd stored
+    leading dimensions and ragged edges (unaligned and checked load paths)."""
+    A, B = stored_pair(130, 257, 67, opA, opB, "int", seed=9, bound=1024)
+    print(f"integer ops {opA}{opB}", flush=True)
+    assert np.array_equal(run(bq, A, B, opA=opA, opB=opB), oracle.gemm(OP_FN[opA](A), OP_FN[opB](B)))
+
+
+def test_transpose_reverses_products(bq):
+    """T(A B) = T(B) T(A) (Sec. III): op T on the stored B and A gives the
+    oracle's transpose of the plain product."""
+    A, B = inputs.pair(64, 48, 40, "uniform", seed=11)
+    CT = run(bq, B, A, opA="T", opB="T")
+    assert oracle.rel_frobenius(CT, oracle.transpose(oracle.gemm(A, B))) <= TOL
+
+
+@pytest.mark.parametrize("opA,opB", [("T", "H"), ("H", "N")])
+def test_transposed_ops_streamed_and_masks(bq, opA, opB):
+    """Transposed operands through the streamed plan and a real-quaternion
+    mask (8 GEMMs)."""
+    A, B = stored_pair(150, 140, 130, opA, opB, "uniform", seed=12)
+    ref = oracle.gemm(OP_FN[opA](A), OP_FN[opB](B))
+    C1 = run(bq, A, B, opA=opA, opB=opB)
+    C2 = run(bq, A, B, opA=opA, opB=opB, streamed=True)
+    assert np.array_equal(C1, C2)
+    assert oracle.rel_frobenius(C2, ref) <= TOL
+    mask = inputs.MASKS["real_quaternion"]
+    A, B = stored_pair(90, 70, 60, opA, opB, "normal", seed=13, mask=mask)
+    got = run(bq, A, B, opA=opA, opB=opB, mask_a=mask, mask_b=mask)
+    assert oracle.rel_frobenius(got, oracle.gemm(OP_FN[opA](A), OP_FN[opB](B))) <= TOL
 
 
 @pytest.mark.parametrize("name", ["real_quaternion", "complex", "real"])
@@ -177,9 +226,9 @@ def test_error_leaves_c_untouched(bq):
 
     A, B = inputs.pair(32, 32, 32, "uniform", seed=11)
     C = torch.full((8, 32, 32), 7.0, dtype=torch.float64, device="cuda")
-    with pytest.raises(bq.BqError) as e:
-        bq.bq_gemm(dev(A), dev(B), C, opA="T")
-    assert e.value.code == 2
+    with pytest.raises(bq.BqError) as e:   # workspace below the streamed minimum
+        bq.bq_gemm(dev(A), dev(B), C, workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == 4
     torch.cuda.synchronize()
     assert torch.all(C == 7.0).item()
 

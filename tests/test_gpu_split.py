@@ -93,6 +93,33 @@ def test_default_slices_accuracy(bq, kind, dist):
     assert err <= TOL
 
 
+OP_FN = {"N": lambda M: M, "T": oracle.transpose, "C": oracle.conj, "H": oracle.herm}
+
+
+@pytest.mark.parametrize("kind,S,opA,opB", [("bf16", 4, "T", "H"), ("int8", 4, "H", "T"), ("fp8", 6, "T", "N")])
+def test_transposed_ops_integer_bit_exact(bq, kind, S, opA, opB):
+    """op T / H in the split form: exponents per row of op(A) and per column
+    of op(B) taken along the stored layout's other dimension."""
+    rng = np.random.default_rng(17)
+    m, k, n = 96, 80, 72
+    A = inputs.blocks(rng, *((k, m) if opA in "TH" else (m, k)), "int", bound=64)
+    B = inputs.blocks(rng, *((n, k) if opB in "TH" else (k, n)), "int", bound=64)
+    print(f"split {kind} S={S} ops {opA}{opB} integer", flush=True)
+    got = run(bq, A, B, kind, S, opA=opA, opB=opB)
+    assert np.array_equal(got, oracle.gemm(OP_FN[opA](A), OP_FN[opB](B)))
+
+
+@pytest.mark.parametrize("kind,S", [("bf16", 7), ("int8", 7), ("fp8", 10)])
+def test_transposed_ops_match_cpu_split_model(bq, kind, S):
+    rng = np.random.default_rng(18)
+    m, k, n = 130, 100, 70
+    A = inputs.blocks(rng, k, m, "logspread")   # stored for op H
+    B = inputs.blocks(rng, n, k, "logspread")   # stored for op T
+    print(f"split {kind} S={S} ops HT vs model", flush=True)
+    ref = bilinear(oracle.herm(A), oracle.transpose(B), Counter(lambda x, y: ozaki.product(x, y, kind, S)))
+    assert oracle.rel_frobenius(run(bq, A, B, kind, S, opA="H", opB="T"), ref) <= 1e-14
+
+
 @pytest.mark.parametrize("kind", ["bf16", "int8"])
 def test_conj_and_masks(bq, kind):
     A, B = inputs.pair(90, 70, 60, "normal", seed=14)
