@@ -167,6 +167,21 @@ def test_plan_counts_match_paper():
     assert B.plan_real_gemms(0x00, 0xFF) == 0
 
 
+@pytest.mark.parametrize("ma,mb,count", [
+    (0x0F, 0xFF, 16),   # real quaternion x biquaternion: 16 (4 real-by-complex pairs, twice)
+    (0xFF, 0x0F, 16),
+    (0xF0, 0xFF, 16),   # purely imaginary-field biquaternion [0,0,0,0,1,1,1,1] x full
+    (0x11, 0xFF, 12),   # complex scalar x biquaternion: 4 complex products, 3 GEMMs each
+    (0x01, 0xFF, 8),    # real scalar field x biquaternion: 8 real products
+    (0x33, 0x33, 12),   # units 1 and i with complex coefficients: 4 complex products (component-wise < bilinear 15)
+])
+def test_plan_counts_general_masks(ma, mb, count):
+    """Active-component patterns beyond the four subalgebras (Sec. III A:
+    absent components are skipped): the planner's min(bilinear,
+    component-wise) real-GEMM count."""
+    assert B.plan_real_gemms(ma, mb) == count
+
+
 def test_degenerate_shapes_validate():
     assert check(mat(0, 5, FAKE), mat(5, 3, 2 * FAKE), mat(0, 3, 3 * FAKE)) == OK
     assert check(mat(4, 0, FAKE), mat(0, 3, 2 * FAKE), mat(4, 3, 3 * FAKE)) == OK

@@ -132,6 +132,22 @@ def test_subalgebra_masks(bq, name):
         assert not np.any(C[c]), c
 
 
+@pytest.mark.parametrize("ma,mb", [(0x0F, 0xFF), (0xFF, 0x0F), (0xF0, 0xFF), (0x11, 0xFF), (0x01, 0xFF),
+                                   (0x33, 0x33), (0xF0, 0xF0), (0x22, 0x44)])
+def test_general_masks(bq, ma, mb):
+    """Active-component patterns beyond the four subalgebras (mixed real
+    quaternion x biquaternion, the imaginary-field pattern [0,0,0,0,1,1,1,1],
+    scalars times biquaternions, two-unit patterns): every output block
+    against the oracle, structurally zero blocks exactly 0."""
+    A, B = inputs.pair(70, 60, 50, "normal", seed=21, mask_a=ma, mask_b=mb)
+    C = run(bq, A, B, mask_a=ma, mask_b=mb)
+    ref = oracle.gemm(A, B)
+    assert oracle.rel_frobenius(C, ref) <= TOL
+    for c in range(8):
+        if not np.any(ref[c]):
+            assert not np.any(C[c]), c
+
+
 def _reach(mask):
     if mask == inputs.REAL:
         return {0}
