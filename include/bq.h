@@ -190,6 +190,44 @@ bq_status_t bq_grouped_plan_launch(bq_grouped_plan_t plan, void* ws, size_t ws_b
 bq_status_t bq_grouped_plan_info(bq_grouped_plan_t plan, int* tile_config, int* dynamic_schedule, int* work_items);
 bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan);
 
+/* ---------------------------------------------------------------------------
+ * Diagonalization of a Hermitian matrix-valued biquaternion (Sec. III and the
+ * Hadamard transformation for diagonalization in the implementation section):
+ * A (n x n, A^dagger = A, i.e. components c1 and c6..c8 symmetric, c2..c5
+ * antisymmetric) is mapped to its complex Hermitian isomorph
+ *   Z(A) = [[Z11, Z12], [Z21, Z22]]  (2n x 2n; eq. mapping-formulas read
+ *   backwards, M = M+ + M-):
+ *   Z11 = (c1 - c6) + i (c2 + c5),   Z12 = (c3 - c8) + i (c4 + c7),
+ *   Z21 = -(c3 + c8) + i (c4 - c7),  Z22 = (c1 + c6) + i (c5 - c2),
+ * whose eigenvalues and eigenvectors are returned.  The components present
+ * select the work:
+ *   - no j or k components (c3, c4, c7, c8 absent): Z is block diagonal; the
+ *     two n x n blocks are solved separately, once when Z22 = Z11 (c2, c6
+ *     absent) or Z22 = conj(Z11) (c5, c6 absent);
+ *   - j and k only (c1, c2, c5, c6 absent) with pure j (c3, c7) or pure k
+ *     (c4, c8): Z is block anti-diagonal and the Hadamard-type transform
+ *     U = [[I, I], [a I, -a I]] / sqrt(2) (a = i for pure j, a = 1 for pure
+ *     k) makes it diag(a Z12, -a Z12): one n x n solve, eigenvalues +-mu;
+ *   - otherwise one 2n x 2n solve.
+ * The complex Hermitian eigensolver is rocSOLVER's zheevd (a library call);
+ * the mapping, the reduction, the eigenvalue merge and the eigenvector
+ * assembly are this library's kernels.
+ *
+ * w:    device, 2n doubles: eigenvalues in ascending order.
+ * V:    device or NULL: eigenvectors of Z(A) as columns, 2n x 2n complex
+ *       (interleaved re, im doubles), column-major with leading dimension
+ *       ldv >= 2n complex elements: Z(A) V = V diag(w), V^dagger V = I.
+ * info: device int or NULL: 0 on success, > 0 if an eigensolve did not
+ *       converge (written asynchronously, like w and V).
+ * Only the part of A the isomorph's lower triangle comes from is read; A
+ * is taken to be Hermitian, not checked.  n == 0 is a no-op.  Errors as for
+ * bq_gemm (validation first, nothing enqueued on error); the workspace is
+ * the caller's, the eigensolver's scratch included (no allocation). */
+bq_status_t bq_heev_workspace_size(bq_handle_t h, int64_t n, unsigned mask, int want_vectors,
+                                   size_t* bytes);
+bq_status_t bq_heev(bq_handle_t h, const bq_matrix_t* A, double* w, double* V, int64_t ldv, int* info,
+                    void* ws, size_t ws_bytes, bq_stream_t stream);
+
 /* Launch tracing (measurement support, not part of the product semantics).
  * While enabled, every kernel the handle enqueues is bracketed by a pair of
  * HIP events recorded on the same stream.  bq_trace_read waits for the
@@ -207,8 +245,13 @@ typedef enum {
   BQ_KERNEL_SPLIT = 12,     /* exponents + digit slices of one operand */
   BQ_KERNEL_SLICE_GEMM = 13, /* one real product from digit slices;
                                flops = pairs * 2 m n k, config = slices */
-  BQ_KERNEL_GROUPED = 14     /* one launch of a batched plan (whole graph);
+  BQ_KERNEL_GROUPED = 14,    /* one launch of a batched plan (whole graph);
                                flops = executed real-GEMM flops of all problems */
+  BQ_KERNEL_HEEV_MAP = 20,   /* isomorph (or reduced block) of a Hermitian
+                               biquaternion; bytes read + written */
+  BQ_KERNEL_HEEV_SOLVE = 21, /* one complex Hermitian eigensolve (zheevd);
+                               m = n = its order, config = 1 with vectors */
+  BQ_KERNEL_HEEV_ASSEMBLE = 22 /* eigenvalue merge + eigenvector assembly */
 } bq_kernel_t;
 
 typedef struct {

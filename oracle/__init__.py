@@ -124,6 +124,15 @@ def iso_inv(Z) -> np.ndarray:
     return np.stack([E.real, E.imag, F.real, F.imag, G.imag, -G.real, H.imag, -H.real])
 
 
+def heev(M):
+    """Eigenvalues (ascending) and eigenvectors (columns) of the complex
+    isomorph of a Hermitian biquaternion M (8, n, n): the diagonalization of
+    the implementation section maps M to Z(M) (eq. mapping-formulas) and
+    solves the complex Hermitian problem; numpy's Hermitian eigensolver is
+    the library step."""
+    return np.linalg.eigh(iso(M))
+
+
 # ---------------------------------------------------------------------------
 # T, *, dagger as a transposition plus per-component sign flips (Sec. III).
 # ---------------------------------------------------------------------------

@@ -6,8 +6,8 @@ loaded on first use and a missing library raises: there is no CPU fallback.
 """
 from ._binding import (BqError, FULL, REAL_QUAT, COMPLEX, REAL, bq_gemm, re_gemm, cx_gemm,
                        rq_gemm, workspace_size, plan_real_gemms, lib, handle, matrix, last_error,
-                       trace_enable, trace_read, GroupedPlan)
+                       trace_enable, trace_read, GroupedPlan, heev, heev_workspace_size)
 
 __all__ = ["BqError", "FULL", "REAL_QUAT", "COMPLEX", "REAL", "bq_gemm", "re_gemm", "cx_gemm",
            "rq_gemm", "workspace_size", "plan_real_gemms", "lib", "handle", "matrix", "last_error",
-           "trace_enable", "trace_read", "GroupedPlan"]
+           "trace_enable", "trace_read", "GroupedPlan", "heev", "heev_workspace_size"]

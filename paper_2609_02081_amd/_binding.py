@@ -77,6 +77,11 @@ _SIGS = [
     ("bq_grouped_plan_info", ctypes.c_int,
      [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     ("bq_grouped_plan_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("bq_heev_workspace_size", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    ("bq_heev", ctypes.c_int,
+     [ctypes.c_void_p, _M, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_size_t, ctypes.c_void_p]),
     ("bq_trace_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("bq_trace_read", ctypes.c_int,
      [ctypes.c_void_p, ctypes.POINTER(BqTraceRecord), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -163,6 +168,40 @@ def workspace_size(m, n, k, mask_a=FULL, mask_b=FULL, prec="fp64", slices=0):
     check(lib().bq_gemm_workspace_size(m, n, k, mask_a, mask_b, PRECS[prec], slices,
                                        ctypes.byref(res), ctypes.byref(mn)))
     return res.value, mn.value
+
+
+def heev_workspace_size(n, mask=FULL, vectors=True, device=0) -> int:
+    out = ctypes.c_size_t()
+    check(lib().bq_heev_workspace_size(handle(device), n, mask, int(bool(vectors)), ctypes.byref(out)))
+    return out.value
+
+
+def heev(A, *, mask=FULL, vectors=True, workspace=None, stream=None):
+    """Eigenvalues (2n, ascending) and optionally eigenvectors of the complex
+    isomorph of the Hermitian biquaternion A (8, n, n): returns (w, V, info)
+    with V (2n, 2n) complex128 whose columns are the eigenvectors (None
+    without vectors) and info a device int tensor (0 = converged)."""
+    import torch
+
+    Am = matrix(A, mask)
+    n = Am.rows
+    dev = (A if _is_tensor(A) else next(t for t in A if t is not None)).device
+    w = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    V = None
+    if vectors:
+        # column-major 2n x 2n complex = row-major storage of V^T
+        Vt = torch.empty((2 * n, 2 * n), dtype=torch.complex128, device=dev)
+    need = heev_workspace_size(n, _mask_of(Am), vectors, dev.index or 0)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    check(lib().bq_heev(handle(dev.index or 0), ctypes.byref(Am), ctypes.c_void_p(w.data_ptr()),
+                        ctypes.c_void_p(Vt.data_ptr()) if vectors else None, 2 * n,
+                        ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                        workspace.numel() * workspace.element_size(), _stream(stream)))
+    if vectors:
+        V = Vt.transpose(0, 1)
+    return w, V, info
 
 
 def plan_real_gemms(mask_a=FULL, mask_b=FULL) -> int:

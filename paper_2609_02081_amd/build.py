@@ -13,7 +13,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbq.so")
-SOURCES = ["bq_engine.cpp", "bq_kernels.hip", "bq_split.hip"]
+SOURCES = ["bq_engine.cpp", "bq_kernels.hip", "bq_split.hip", "bq_heev.hip"]
+# The eigensolves of bq_heev call rocSOLVER (with rocBLAS for its handle).
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -47,7 +49,7 @@ def build(verbose: bool = False) -> str:
         _run([HIPCC, *COMMON, *EXTRA.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -3,6 +3,7 @@
 // eq. bilinearH or the component-wise form, whichever needs fewer real
 // GEMMs for the active components), workspace carving and kernel launches.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <fstream>
 #include <sstream>
@@ -11,6 +12,9 @@
 #include <cstring>
 #include <string>
 #include <vector>
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include "bq.h"
 #include "bq_internal.h"
@@ -26,6 +30,7 @@ struct bq_handle_s {
   std::string arch;
   bool trace = false;
   std::vector<TraceSlot> pending;
+  rocblas_handle rb = nullptr;  // eigensolver calls; its device memory is always the caller's workspace
 };
 
 namespace {
@@ -759,6 +764,19 @@ bq_status_t bq_create(bq_handle_t* h, int device) {
   hh->device = device;
   hh->cu_count = prop.multiProcessorCount;
   hh->arch = prop.gcnArchName;
+  // The eigensolver's handle lives on the same device.
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if ((e = hipSetDevice(device)) != hipSuccess) {
+    delete hh;
+    return hip_fail(e, "hipSetDevice");
+  }
+  const rocblas_status rs = rocblas_create_handle(&hh->rb);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  if (rs != rocblas_status_success) {
+    delete hh;
+    return fail(BQ_ERR_HIP, "rocblas_create_handle failed");
+  }
   *h = hh;
   return BQ_OK;
 }
@@ -769,6 +787,7 @@ bq_status_t bq_destroy(bq_handle_t h) {
       (void)hipEventDestroy(t.start);
       (void)hipEventDestroy(t.stop);
     }
+    if (h->rb) (void)rocblas_destroy_handle(h->rb);
   }
   delete h;
   return BQ_OK;
@@ -1331,6 +1350,282 @@ bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan) {
   if (plan->d_comb) (void)hipFree(plan->d_comb);
   if (plan->d_prefix) (void)hipFree(plan->d_prefix);
   delete plan;
+  return BQ_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Hermitian eigenproblem (diagonalization through the complex isomorph)
+// ===========================================================================
+namespace {
+
+// Weights of the isomorph's quadrants Z11, Z12, Z21, Z22 over c1..c8
+// (eq. mapping-formulas read backwards: Z = M+ + M-, E = c1 + i c2,
+// F = c3 + i c4, G = -c6 + i c5, H = -c8 + i c7).
+constexpr double kIsoRe[4][8] = {{1, 0, 0, 0, 0, -1, 0, 0},
+                                 {0, 0, 1, 0, 0, 0, 0, -1},
+                                 {0, 0, -1, 0, 0, 0, 0, -1},
+                                 {1, 0, 0, 0, 0, 1, 0, 0}};
+constexpr double kIsoIm[4][8] = {{0, 1, 0, 0, 1, 0, 0, 0},
+                                 {0, 0, 0, 1, 0, 0, 1, 0},
+                                 {0, 0, 0, 1, 0, 0, -1, 0},
+                                 {0, -1, 0, 0, 1, 0, 0, 0}};
+
+enum HeevCase { HEEV_FULL, HEEV_BLOCKS, HEEV_BLOCKS_EQUAL, HEEV_BLOCKS_CONJ, HEEV_ANTI_J, HEEV_ANTI_K };
+
+HeevCase heev_case(unsigned mask) {
+  auto has = [&](int c) { return (mask >> c & 1) != 0; };  // c: 0-based component
+  const bool jk = has(2) || has(3) || has(6) || has(7);
+  const bool field = has(0) || has(1) || has(4) || has(5);
+  if (!jk) {
+    if (!has(1) && !has(5)) return HEEV_BLOCKS_EQUAL;  // Z11 = Z22 = c1 + i c5
+    if (!has(4) && !has(5)) return HEEV_BLOCKS_CONJ;   // Z22 = conj(Z11), Z11 = c1 + i c2
+    return HEEV_BLOCKS;
+  }
+  if (!field) {
+    if (!has(3) && !has(7)) return HEEV_ANTI_J;  // j only: a = i
+    if (!has(2) && !has(6)) return HEEV_ANTI_K;  // k only: a = 1
+  }
+  return HEEV_FULL;
+}
+
+struct HeevLayout {
+  int64_t order = 0;  // order of each eigensolve
+  int solves = 0;
+  size_t z = 0, x1 = 0, x2 = 0, d1 = 0, d2 = 0, e = 0, info = 0, src = 0, scratch = 0;
+  size_t scratch_bytes = 0, total = 0;
+  bool z_in_ws = false;
+};
+
+// Eigensolver scratch for one solve (rocBLAS device-memory size query: the
+// call returns before touching its pointers, which only need to be non-null).
+bool heev_scratch(rocblas_handle rb, int64_t order, bool vectors, size_t* bytes) {
+  *bytes = 0;
+  if (order == 0) return true;
+  if (rocblas_start_device_memory_size_query(rb) != rocblas_status_success) return false;
+  auto* fake_c = reinterpret_cast<rocblas_double_complex*>(uintptr_t(256));
+  auto* fake_d = reinterpret_cast<double*>(uintptr_t(256));
+  auto* fake_i = reinterpret_cast<rocblas_int*>(uintptr_t(256));
+  (void)rocsolver_zheevd(rb, vectors ? rocblas_evect_original : rocblas_evect_none, rocblas_fill_lower,
+                         (rocblas_int)order, fake_c, (rocblas_int)order, fake_d, fake_d, fake_i);
+  return rocblas_stop_device_memory_size_query(rb, bytes) == rocblas_status_success;
+}
+
+bool heev_layout(rocblas_handle rb, int64_t n, unsigned mask, bool vectors, HeevLayout* L) {
+  const HeevCase hc = heev_case(mask);
+  HeevLayout l;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  const size_t cplx = 16;
+  if (hc == HEEV_FULL) {
+    l.order = 2 * n;
+    l.solves = 1;
+    l.z_in_ws = !vectors;  // with vectors the isomorph is built in V and solved in place
+    if (l.z_in_ws) l.z = take(size_t(l.order) * size_t(l.order) * cplx);
+  } else {
+    l.order = n;
+    l.solves = hc == HEEV_BLOCKS ? 2 : 1;
+    l.x1 = take(size_t(n) * size_t(n) * cplx);
+    if (l.solves == 2) l.x2 = take(size_t(n) * size_t(n) * cplx);
+    l.d1 = take(size_t(n) * 8);
+    if (l.solves == 2) l.d2 = take(size_t(n) * 8);
+    if (vectors) l.src = take(size_t(2 * n) * 8);
+  }
+  l.e = take(size_t(std::max<int64_t>(l.order, 1)) * 8);
+  l.info = take(2 * sizeof(int));
+  if (!heev_scratch(rb, l.order, vectors, &l.scratch_bytes)) return false;
+  l.scratch = take(l.scratch_bytes);
+  l.total = off;
+  *L = l;
+  return true;
+}
+
+unsigned mask_of(const bq_matrix_t* M) {
+  unsigned m = 0;
+  for (int c = 0; c < 8; ++c)
+    if (M->comp[c]) m |= 1u << c;
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+bq_status_t bq_heev_workspace_size(bq_handle_t h, int64_t n, unsigned mask, int want_vectors, size_t* bytes) {
+  if (!bytes) return fail(BQ_ERR_INVALID_VALUE, "bytes is null");
+  *bytes = 0;
+  if (bq_status_t st = check_handle(h); st != BQ_OK) return st;
+  if (n < 0) return fail(BQ_ERR_INVALID_VALUE, "negative dimension");
+  if (mask > 0xFFu) return fail(BQ_ERR_INVALID_VALUE, "mask has bits above 7");
+  if (2 * n > INT32_MAX) return fail(BQ_ERR_UNSUPPORTED, "2n above the eigensolver's 32-bit order");
+  if (n == 0) return BQ_OK;
+  HeevLayout L;
+  if (!heev_layout(h->rb, n, mask, want_vectors != 0, &L)) return fail(BQ_ERR_HIP, "eigensolver size query failed");
+  *bytes = L.total;
+  return BQ_OK;
+}
+
+bq_status_t bq_heev(bq_handle_t h, const bq_matrix_t* A, double* w, double* V, int64_t ldv, int* info, void* ws,
+                    size_t ws_bytes, bq_stream_t stream) {
+  if (!A) return fail(BQ_ERR_INVALID_VALUE, "A is null");
+  if (A->rows != A->cols) return fail(BQ_ERR_INVALID_VALUE, "A must be square");
+  const int64_t n = A->rows, N = 2 * n;
+  if (n < 0) return fail(BQ_ERR_INVALID_VALUE, "negative dimension");
+  if (A->ld < std::max<int64_t>(1, n)) return fail(BQ_ERR_INVALID_VALUE, "A: ld < max(1, cols)");
+  for (int c = 0; c < 8; ++c)
+    if (A->comp[c] && misaligned(A->comp[c])) return fail(BQ_ERR_INVALID_VALUE, "A: component not 8-byte aligned");
+  if (N > INT32_MAX) return fail(BQ_ERR_UNSUPPORTED, "2n above the eigensolver's 32-bit order");
+  if (n > 0 && !w) return fail(BQ_ERR_INVALID_VALUE, "w is null");
+  if (V && ldv < std::max<int64_t>(1, N)) return fail(BQ_ERR_INVALID_VALUE, "ldv < 2n");
+  if (V && ldv > INT32_MAX) return fail(BQ_ERR_UNSUPPORTED, "ldv above the eigensolver's 32-bit range");
+  if (ws_bytes > 0 && !ws) return fail(BQ_ERR_INVALID_VALUE, "ws is null but ws_bytes > 0");
+  if (bq_status_t st = check_handle(h); st != BQ_OK) return st;
+  if (n == 0) return BQ_OK;
+  const unsigned mask = mask_of(A);
+  const HeevCase hc = heev_case(mask);
+  const bool vectors = V != nullptr;
+  HeevLayout L;
+  if (!heev_layout(h->rb, n, mask, vectors, &L)) return fail(BQ_ERR_HIP, "eigensolver size query failed");
+  if (ws_bytes < L.total)
+    return fail(BQ_ERR_WORKSPACE, "workspace " + std::to_string(ws_bytes) + " B < " + std::to_string(L.total) + " B");
+  // Outputs against the input and the workspace.
+  {
+    std::vector<Range> ins;
+    for (int c = 0; c < 8; ++c)
+      if (A->comp[c]) ins.push_back(block_range(A->comp[c], n, n, A->ld));
+    const uintptr_t wl = reinterpret_cast<uintptr_t>(ws);
+    if (L.total > 0) ins.push_back({wl, wl + L.total});
+    std::vector<Range> outs = {{reinterpret_cast<uintptr_t>(w), reinterpret_cast<uintptr_t>(w) + uintptr_t(N) * 8}};
+    if (V) {
+      const uintptr_t v0 = reinterpret_cast<uintptr_t>(V);
+      outs.push_back({v0, v0 + (uintptr_t(N - 1) * uintptr_t(ldv) + uintptr_t(N)) * 16});
+    }
+    if (info) outs.push_back({reinterpret_cast<uintptr_t>(info), reinterpret_cast<uintptr_t>(info) + sizeof(int)});
+    for (size_t i = 0; i < outs.size(); ++i) {
+      for (const Range& r : ins)
+        if (overlaps(outs[i], r)) return fail(BQ_ERR_ALIAS, "an output overlaps A or the workspace");
+      for (size_t j = i + 1; j < outs.size(); ++j)
+        if (overlaps(outs[i], outs[j])) return fail(BQ_ERR_ALIAS, "two outputs overlap");
+    }
+  }
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  auto at = [&](size_t off) { return reinterpret_cast<void*>(base + off); };
+  if (rocblas_set_stream(h->rb, s) != rocblas_status_success) return fail(BQ_ERR_HIP, "rocblas_set_stream failed");
+  if (rocblas_set_workspace(h->rb, at(L.scratch), L.scratch_bytes) != rocblas_status_success)
+    return fail(BQ_ERR_HIP, "rocblas_set_workspace failed");
+  double* E = static_cast<double*>(at(L.e));
+  int* inf = static_cast<int*>(at(L.info));
+  const rocblas_evect ev = vectors ? rocblas_evect_original : rocblas_evect_none;
+  const double in_bytes = double(__builtin_popcount(mask)) * double(n) * double(n) * 8.0;
+
+  auto map = [&](int quadrant, Cplx scale, int64_t R, double* out, int64_t ldo) -> hipError_t {
+    bq::HeevMapArgs a{};
+    for (int c = 0; c < 8; ++c) a.src[c] = A->comp[c];
+    a.lds = A->ld;
+    a.n = n;
+    a.R = R;
+    for (int q = 0; q < 4; ++q) {
+      const int src_q = R == N ? q : quadrant;
+      for (int c = 0; c < 8; ++c) {
+        // (scale) * (re + i im) per component weight
+        const double wr = kIsoRe[src_q][c], wi = kIsoIm[src_q][c];
+        a.wr[q][c] = scale.re * wr - scale.im * wi;
+        a.wi[q][c] = scale.re * wi + scale.im * wr;
+      }
+    }
+    a.out = out;
+    a.ldo = ldo;
+    Tracer tr(h, s, BQ_KERNEL_HEEV_MAP, -1, R, R, 0, 0.0, in_bytes + double(R) * double(R) * 16.0);
+    hipError_t e = bq::launch_heev_map(a, s);
+    tr.done();
+    return e;
+  };
+  auto solve = [&](double* Z, int64_t ld, double* D, int* inf_out) -> bq_status_t {
+    Tracer tr(h, s, BQ_KERNEL_HEEV_SOLVE, vectors ? 1 : 0, L.order, L.order, 0, 0.0, 0.0);
+    const rocblas_status rs = rocsolver_zheevd(h->rb, ev, rocblas_fill_lower, (rocblas_int)L.order,
+                                               reinterpret_cast<rocblas_double_complex*>(Z), (rocblas_int)ld, D, E,
+                                               inf_out);
+    tr.done();
+    if (rs != rocblas_status_success)
+      return fail(BQ_ERR_HIP, std::string("rocsolver_zheevd: ") + rocblas_status_to_string(rs));
+    return BQ_OK;
+  };
+
+  hipError_t e = hipSuccess;
+  if (hc == HEEV_FULL) {
+    double* Z = vectors ? V : static_cast<double*>(at(L.z));
+    const int64_t ldz = vectors ? ldv : N;
+    if ((e = map(0, {1.0, 0.0}, N, Z, ldz)) != hipSuccess) return hip_fail(e, "isomorph launch");
+    if (bq_status_t st = solve(Z, ldz, w, inf); st != BQ_OK) return st;
+    if (info && (e = bq::launch_heev_info(inf, nullptr, info, s)) != hipSuccess) return hip_fail(e, "info launch");
+    return BQ_OK;
+  }
+
+  double* X1 = static_cast<double*>(at(L.x1));
+  double* X2 = L.solves == 2 ? static_cast<double*>(at(L.x2)) : nullptr;
+  double* D1 = static_cast<double*>(at(L.d1));
+  double* D2 = L.solves == 2 ? static_cast<double*>(at(L.d2)) : nullptr;
+  int64_t* src = vectors ? static_cast<int64_t*>(at(L.src)) : nullptr;
+  bq::HeevAsmArgs asmb{};
+  asmb.n = n;
+  asmb.ldx = n;
+  asmb.src = src;
+  asmb.V = V;
+  asmb.ldv = ldv;
+  const double r2 = 1.0 / std::sqrt(2.0);
+  double s2 = 1.0;
+  int rev = 0;
+  const double* list2 = nullptr;
+  if (hc == HEEV_ANTI_J || hc == HEEV_ANTI_K) {
+    // U^dagger Z U = diag(a Z12, -a Z12) with U = [[I, I], [a I, -a I]] / sqrt(2).
+    const Cplx a = hc == HEEV_ANTI_J ? Cplx{0.0, 1.0} : Cplx{1.0, 0.0};
+    if ((e = map(1, a, n, X1, n)) != hipSuccess) return hip_fail(e, "reduced block launch");
+    if (bq_status_t st = solve(X1, n, D1, inf); st != BQ_OK) return st;
+    list2 = D1;
+    s2 = -1.0;
+    rev = 1;
+    // mu: [x; a x] / sqrt 2, -mu: [x; -a x] / sqrt 2
+    asmb.xt[0] = asmb.xb[0] = asmb.xt[1] = asmb.xb[1] = X1;
+    asmb.ct[0][0] = asmb.ct[1][0] = r2;
+    asmb.cb[0][0] = r2 * a.re;
+    asmb.cb[0][1] = r2 * a.im;
+    asmb.cb[1][0] = -r2 * a.re;
+    asmb.cb[1][1] = -r2 * a.im;
+    asmb.rev2 = 1;
+  } else {
+    if ((e = map(0, {1.0, 0.0}, n, X1, n)) != hipSuccess) return hip_fail(e, "block launch");
+    if (bq_status_t st = solve(X1, n, D1, inf); st != BQ_OK) return st;
+    asmb.xt[0] = X1;
+    asmb.ct[0][0] = 1.0;
+    if (hc == HEEV_BLOCKS) {
+      if ((e = map(3, {1.0, 0.0}, n, X2, n)) != hipSuccess) return hip_fail(e, "block launch");
+      if (bq_status_t st = solve(X2, n, D2, inf + 1); st != BQ_OK) return st;
+      list2 = D2;
+      asmb.xb[1] = X2;
+    } else {
+      list2 = D1;  // Z22 = Z11, or conj(Z11): same eigenvalues
+      asmb.xb[1] = X1;
+      asmb.conj_b[1] = hc == HEEV_BLOCKS_CONJ;
+    }
+    asmb.cb[1][0] = 1.0;
+  }
+  {
+    Tracer tr(h, s, BQ_KERNEL_HEEV_ASSEMBLE, -1, N, vectors ? N : 0, 0, 0.0,
+              double(N) * 24.0 + (vectors ? double(N) * double(N) * 16.0 * 2.0 : 0.0));
+    e = bq::launch_heev_merge(D1, n, list2, n, s2, rev, w, src, s);
+    if (e == hipSuccess && vectors) e = bq::launch_heev_assemble(asmb, s);
+    tr.done();
+    if (e != hipSuccess) return hip_fail(e, "eigenvalue merge / vector assembly launch");
+  }
+  if (info && (e = bq::launch_heev_info(inf, L.solves == 2 ? inf + 1 : nullptr, info, s)) != hipSuccess)
+    return hip_fail(e, "info launch");
   return BQ_OK;
 }
 

@@ -113,6 +113,31 @@ struct GroupedItem {
   int tm, tn;
 };
 
+// Complex linear map of the 8 components into an R x R complex buffer
+// (heev_map_kernel): quadrant q (R = 2n: 0..3 = 11, 12, 21, 22; R = n: 0).
+struct HeevMapArgs {
+  const double* src[8];
+  int64_t lds;
+  int64_t n, R;
+  double wr[4][8], wi[4][8];
+  double* out;  // interleaved complex, row-major, stored conjugated
+  int64_t ldo;  // complex elements
+};
+
+// Eigenvector assembly (heev_assemble_kernel): lists 0 and 1 of the merge.
+struct HeevAsmArgs {
+  int64_t n;
+  const double* xt[2];  // top-half source per list (column-major n x n complex) or null
+  const double* xb[2];  // bottom-half source per list or null
+  int64_t ldx;
+  double ct[2][2], cb[2][2];  // complex coefficients (re, im)
+  int conj_t[2], conj_b[2];
+  const int64_t* src;
+  int rev2;
+  double* V;
+  int64_t ldv;
+};
+
 struct TileConfig {
   int bm, bn, bk, wm, wn;
 };
@@ -142,5 +167,11 @@ int slice_kstep(int et);              // k per MFMA step (32 or 64)
 int slice_beta(int et);
 int slice_head(int et);
 int slice_flush_steps(int et, int S);  // k-steps per exact level accumulation
+// Hermitian eigenproblem kernels (bq_heev.hip).
+hipError_t launch_heev_map(const HeevMapArgs& a, hipStream_t s);
+hipError_t launch_heev_merge(const double* x1, int64_t n1, const double* x2, int64_t n2, double s2, int rev,
+                             double* w, int64_t* src, hipStream_t s);
+hipError_t launch_heev_assemble(const HeevAsmArgs& a, hipStream_t s);
+hipError_t launch_heev_info(const int* a, const int* b, int* out, hipStream_t s);
 
 }  // namespace bq

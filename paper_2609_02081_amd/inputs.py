@@ -132,6 +132,19 @@ def hermitian_blocks(params: dict, device="cpu"):
     return out
 
 
+def hermitian_random(n: int, mask: int = FULL, seed: int = 1, dist: str = "normal") -> np.ndarray:
+    """(8, n, n) float64 Hermitian biquaternion (A^dagger = A): components 1
+    and 6..8 symmetric, 2..5 antisymmetric (the dagger sign pattern);
+    components outside `mask` are zero."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((8, n, n), dtype=np.float64)
+    for c in range(8):
+        if mask >> c & 1:
+            X = _draw(rng, (n, n), dist, 1024)
+            out[c] = 0.5 * (X + X.T) if c in (0, 5, 6, 7) else 0.5 * (X - X.T)
+    return out
+
+
 def device_uniform(n_rows: int, n_cols: int, seed: int, device, count: int = 8):
     """(count, rows, cols) float64 uniform[-1, 1] drawn on `device`."""
     import torch
