@@ -100,6 +100,52 @@ def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, copy_bytes
     print(json.dumps(out))
 
 
+def heev_leg(bq, inputs, torch, n, log):
+    """Diagonalization of a Hermitian biquaternion, n x n (complex order 2n):
+    the benchmark's Fock-like generator (U diag(lambda) U^H, known signed
+    spectrum 1e0..1e-8), full problem with eigenvectors; then a pure-k input
+    of the same n through the Hadamard-reduced path.  The error is against
+    the generator's known eigenvalues."""
+    import numpy as np
+
+    p = inputs.hermitian_params(n, 7, "fock")
+    A = inputs.hermitian_blocks(p, "cuda")
+    out = {"workload": f"Hermitian biquaternion n={n} (complex order {2 * n}), Fock-like spectrum, eigenvectors",
+           "solver": "rocSOLVER zheevd on the isomorph (library); mapping, reduction, merge and assembly here"}
+
+    def timed(X, mask):
+        need = bq.heev_workspace_size(n, mask, True)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        bq.heev(X, mask=mask, workspace=ws)
+        torch.cuda.synchronize()
+        bq.trace_read()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        w, V, info = bq.heev(X, mask=mask, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        recs = bq.trace_read()
+        own = sum(r["ms"] for r in recs if r["kernel"] in ("heev_map", "heev_assemble"))
+        return e0.elapsed_time(e1), own, w, int(info.item())
+
+    ms, own, w, info = timed(A, 0xFF)
+    err = float(np.max(np.abs(w.cpu().numpy() - np.sort(p["lam"]))))
+    out.update({"full_ms": round(ms, 2), "full_own_kernels_ms": round(own, 2), "info": info,
+                "max_abs_eigenvalue_error_vs_known": err})
+    log(f"heev full n={n}: {ms:.1f} ms, eigenvalue error {err:.2e}")
+    del A, w
+    torch.cuda.empty_cache()
+    K = torch.from_numpy(inputs.hermitian_random(n, 0x88, seed=8)).to("cuda")
+    ms_k, own_k, w, info_k = timed(K, 0x88)
+    out.update({"pure_k_reduced_ms": round(ms_k, 2), "pure_k_own_kernels_ms": round(own_k, 2),
+                "reduction_speedup_vs_full": round(ms / ms_k, 2)})
+    log(f"heev pure k n={n}: {ms_k:.1f} ms (Hadamard-reduced)")
+    del K, w
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(bq, inputs, torch, count, log):
     """count products, square sizes log-uniform over 64..1536 (seed 5),
     uniform[-1, 1]: one grouped plan (graph of a pre-combination launch and
@@ -167,6 +213,8 @@ def main():
                     help="rows/cols of the sub-block the oracle recomputes (0: skip)")
     ap.add_argument("--split", default="split_int8,split_bf16,split_fp8",
                     help="split-precision forms timed beside FP64 on the same inputs ('' to skip)")
+    ap.add_argument("--heev", type=int, default=4096,
+                    help="n of the diagonalization leg (complex order 2n; 0 to skip)")
     ap.add_argument("--batched", type=int, default=512,
                     help="products in the batched leg (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -334,10 +382,16 @@ def main():
         log(f"oracle {t_cpu:.1f}s, sampled rel Frobenius error {rel_err:.3e}")
 
     batched = None
-    if args.batched > 0:
+    heev = None
+    if args.batched > 0 or args.heev > 0:
         del A, B, C
         torch.cuda.empty_cache()
+    if args.batched > 0:
         batched = batched_leg(bq, inputs, torch, args.batched, log)
+    if args.heev > 0:
+        bq.trace_enable(True)
+        heev = heev_leg(bq, inputs, torch, args.heev, log)
+        bq.trace_enable(False)
 
     out = {"metric": METRIC, "value": round(eff_tflops, 3), "unit": "effective TFLOP/s (64 real GEMMs counted)",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -350,7 +404,7 @@ def main():
            "mfma_frac_of_fp64_peak": round(exec_tflops / PEAK_FP64_TFLOPS, 4),
            "rel_err_sampled_vs_oracle": rel_err,
            "roofline": roofline, "combine": combine, "cpu_baseline": cpu,
-           "split_precision": split, "batched": batched}
+           "split_precision": split, "batched": batched, "diagonalization": heev}
     print(json.dumps(out), flush=True)
 
 

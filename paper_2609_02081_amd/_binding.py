@@ -36,7 +36,8 @@ class BqTraceRecord(ctypes.Structure):
 
 
 KERNEL_NAMES = {0: "gemm_gauss", 1: "gemm_rc", 2: "gemm_cr", 3: "gemm_rr", 10: "combine", 11: "fill",
-                12: "split", 13: "slice_gemm", 14: "grouped"}
+                12: "split", 13: "slice_gemm", 14: "grouped", 20: "heev_map", 21: "heev_solve",
+                22: "heev_assemble"}
 
 
 class BqError(RuntimeError):
