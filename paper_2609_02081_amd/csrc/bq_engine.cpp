@@ -401,12 +401,12 @@ void tile_order(int* xcd, int* group) {
   }
 }
 
-// Slice-GEMM block shape (BQ_SLICE_VARIANT = 0 .. 3 overrides the default).
+// Slice-GEMM block shape (BQ_SLICE_VARIANT = 0 .. 4 overrides the default).
 int slice_variant() {
   const char* e = std::getenv("BQ_SLICE_VARIANT");
   if (!e || !*e) return -1;
   const int v = std::atoi(e);
-  return (v >= 0 && v <= 3) ? v : -1;
+  return (v >= 0 && v <= 4) ? v : -1;
 }
 
 // BQ_SLICE_FLUSH = f > 0 flushes the level sums at least every f k-steps
@@ -519,7 +519,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     }
     if (sg.ntgt == 0) return hipSuccess;
     const int variant = bq::resolve_slice_variant(pr.et, pr.S, slice_variant());
-    const int tiled = bq::slice_variant_tiled(variant) ? 1 : 0;
+    const int tiled = bq::slice_variant_tiled(variant);
     // The left factor takes one exponent per row of op(A): along the stored
     // rows (row kernels) for N and C, along the stored columns (column
     // kernels, which also transpose the digits) for T and H; the right factor

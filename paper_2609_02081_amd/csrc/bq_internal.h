@@ -82,7 +82,7 @@ struct SplitArgs {
   int beta;                    // digit width in bits
   int head;                    // exponent headroom: row/column exponent = frexp exponent + head
   int left;
-  int tiled;                   // digit layout: 0 = D[s][row][kk]; 1 = 64-row x one-k-step tiles (slice_tile_offset)
+  int tiled;                   // digit layout: 0 = D[s][row][kk]; 1, 2 = 64-row x one-k-step tiles of 64- or 32-byte rows
 };
 
 constexpr int kMaxSliceTargets = 8;
@@ -160,7 +160,7 @@ hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_pr
 hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t s);
 hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t s);  // variant -1: default
 int resolve_slice_variant(int et, int S, int variant);  // the shape launch_slice_gemm runs
-bool slice_variant_tiled(int variant);                   // digits must be written tiled
+int slice_variant_tiled(int variant);                    // digit layout the shape reads (SplitArgs::tiled)
 int max_slices(int et);
 int slice_block_rows(int et, int S);  // rows of a slice-GEMM block tile (128 or 64)
 int slice_kstep(int et);              // k per MFMA step (32 or 64)

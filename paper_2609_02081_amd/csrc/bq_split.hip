@@ -105,15 +105,30 @@ __device__ __forceinline__ int swz_chunk(int r, int ch) {
   else return ch ^ ((r >> 2) & 3);
 }
 
-// Tiled digit layout (direct-to-LDS slice GEMM, 64-byte tile rows): within
-// one slice, the 64 rows x one k-step (BK elements, 64 bytes) of row tile
-// rt, k-step kt form one 4 KB block at (rt * nk + kt) * 4096, stored in the
-// LDS order (row r at r * 64, logical chunk ch at position swz_chunk(r, ch)),
-// so that a straight 4 KB copy lands the tile ready for fragment reads.
+// Tiled digit layouts (direct-to-LDS slice GEMMs): within one slice, the 64
+// rows x one k-step (RB = 64 or 32 bytes per row) of row tile rt, k-step kt
+// form one 64 RB-byte block at (rt * nk + kt) * 64 RB, stored in the LDS
+// order (row r at r * RB, logical 16-byte chunk ch at the swizzled position),
+// so that a straight copy lands the tile ready for fragment reads.
+// Rows of 32 bytes (two chunks): a 16-byte fragment read has 8 lanes on 8
+// consecutive rows at one chunk, rows r and r + 4 share banks, so the chunk
+// position flips with row bit 2.
+__device__ __forceinline__ int swz_chunk32(int r, int ch) { return ch ^ ((r >> 2) & 1); }
+
+template <int RB>
 __device__ __forceinline__ int64_t slice_tile_offset(int64_t r, int64_t byte_in_row, int64_t row_bytes) {
-  const int64_t nk = row_bytes >> 6, kt = byte_in_row >> 6;
-  const int rr = (int)(r & 63), b = (int)(byte_in_row & 63);
-  return ((r >> 6) * nk + kt) * 4096 + rr * 64 + swz_chunk<16>(rr, b >> 4) * 16 + (b & 15);
+  const int64_t nk = row_bytes / RB, kt = byte_in_row / RB;
+  const int rr = (int)(r & 63), b = (int)(byte_in_row % RB);
+  const int pos = RB == 64 ? swz_chunk<16>(rr, b >> 4) : swz_chunk32(rr, b >> 4);
+  return ((r >> 6) * nk + kt) * (64 * RB) + rr * RB + pos * 16 + (b & 15);
+}
+
+// Byte offset of the digit at (row r, byte b of the row) in one slice, for
+// layout `tiled` (0: row-major with rows of row_bytes).
+__device__ __forceinline__ int64_t digit_offset(int tiled, int64_t r, int64_t b, int64_t row_bytes) {
+  if (tiled == 1) return slice_tile_offset<64>(r, b, row_bytes);
+  if (tiled == 2) return slice_tile_offset<32>(r, b, row_bytes);
+  return r * row_bytes + b;
 }
 
 // Digits of one element: q[0..S-1] from x and its row/column exponent.
@@ -164,9 +179,7 @@ __global__ void __launch_bounds__(256) split_digits_left(const SplitArgs a, cons
   constexpr int ES = ET == 0 ? 2 : 1;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    // element offset (row-major digits) or byte offset (tiled digits)
-    const int64_t o = a.tiled ? (int64_t)s * a.slice_stride * ES + slice_tile_offset(r, kk0 * ES, a.kp * ES)
-                              : ((int64_t)s * a.slice_stride + r * a.kp + kk0) * ES;
+    const int64_t o = (int64_t)s * a.slice_stride * ES + digit_offset(a.tiled, r, kk0 * ES, a.kp * ES);
     if constexpr (ET == 0) {
       i4v v;
 #pragma unroll
@@ -227,8 +240,7 @@ __global__ void __launch_bounds__(256) split_digits_right(const SplitArgs a, con
     const int rem = w % (64 * PIECES);
     const int cc = rem / PIECES, p = rem % PIECES;
     const i4v v = *reinterpret_cast<const i4v*>(&tile[s][cc][p * 16]);
-    const int64_t o = a.tiled ? slice_tile_offset(c0 + cc, k0 * ES + p * 16, a.kp * ES)
-                              : ((c0 + cc) * a.kp + k0) * ES + p * 16;
+    const int64_t o = digit_offset(a.tiled, c0 + cc, k0 * ES + p * 16, a.kp * ES);
     *reinterpret_cast<i4v*>(static_cast<unsigned char*>(out) + (int64_t)s * a.slice_stride * ES + o) = v;
   }
 }
@@ -696,6 +708,222 @@ slice_gemm_dma(const SliceGemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Slice GEMM on the 32 x 32 MFMA shapes (BF16: v_mfma_f32_32x32x16_bf16,
+// INT8: v_mfma_i32_32x32x32_i8; checked with one-wave probes: A lane l holds
+// row l % 32, k = 16 (l / 32) bytes on; B the same per column; D lane l,
+// element v holds row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32).  A k-step
+// is 32 bytes of each digit row, so a 128 x 64 block of 8 waves (32 x 32 each,
+// two waves per SIMD) keeps two LDS stages of S slices within 160 KB and
+// moves a quarter fewer bytes per MFMA than the 64 x 64 block.  Digits in the
+// tiled layout of 32-byte rows; per k-step a stage holds S A tiles (128 rows,
+// two 64-row tiles) and S B tiles (64 rows), copied straight into LDS in 1 KB
+// pieces, wave w taking pieces w, w + 8, ...  Level sums as in
+// slice_gemm_dma.
+// ---------------------------------------------------------------------------
+typedef int i16v __attribute__((ext_vector_type(16)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// Workgroup barrier without the memory fence of __syncthreads (which would
+// wait for every load in flight, prefetches included): the kernels order
+// their LDS traffic themselves (wait_vm before, fragment reads consumed
+// before the barrier).
+__device__ __forceinline__ void block_sync() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// s_waitcnt vmcnt(N): wait until at most N vector-memory loads are pending.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  else if constexpr (N == 1) asm volatile("s_waitcnt vmcnt(1)" ::: "memory");
+  else if constexpr (N == 2) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+  else if constexpr (N == 3) asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+  else if constexpr (N == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  else if constexpr (N == 5) asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
+  else if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+  else if constexpr (N == 7) asm volatile("s_waitcnt vmcnt(7)" ::: "memory");
+  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // larger counts: wait for all (correct, slower)
+}
+
+template <int ET>
+struct SliceTraits32;
+template <>
+struct SliceTraits32<0> {
+  static constexpr int ES = 2, BETA = SliceTraits<0>::BETA;
+  typedef bf16x8 frag_t;
+  typedef f16v acc_t;
+  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct SliceTraits32<2> {
+  static constexpr int ES = 1, BETA = SliceTraits<2>::BETA;
+  typedef i4v frag_t;
+  typedef i16v acc_t;
+  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+  }
+};
+
+// Output of one 32 x 32 wave tile at (r0, c0): exponent scaling, then
+// coef * T into every target block.
+__device__ __forceinline__ void store_tile32(const SliceGemmArgs& g, const double (&acc)[16], int64_t r0, int64_t c0,
+                                             int lane) {
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t r = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int64_t c = c0 + (lane & 31);
+    if (r >= g.m || c >= g.n) continue;
+    const int ea = g.ea[r], eb = g.eb[c];
+    const double t = (ea == INT_MIN || eb == INT_MIN) ? 0.0 : ldexp(acc[v], ea + eb);
+    const int64_t off = r * g.ldc + c;
+    for (int q = 0; q < g.ntgt; ++q) {
+      double val = g.coef[q] * t;
+      if (g.mode[q] == TGT_ACCUM) val += g.c[q][off];
+      g.c[q][off] = val;
+    }
+  }
+}
+
+template <int ET, int S>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+slice_gemm_x32(const SliceGemmArgs g) {
+  typedef SliceTraits32<ET> Tr;
+  typedef typename Tr::frag_t frag_t;
+  typedef typename Tr::acc_t acc_t;
+  constexpr int ES = Tr::ES, BETA = Tr::BETA;
+  constexpr int BM = 128, BN = 64, RB = 32, TILE = 64 * RB;  // 2 KB per 64-row tile
+  constexpr int A_SLICE = BM * RB, B_SLICE = BN * RB;
+  constexpr int A_BYTES = S * A_SLICE;
+  constexpr int STAGE = A_BYTES + S * B_SLICE;
+  constexpr int PIECES = STAGE / 1024;  // 6 S
+  // Three stages when they fit: the loads of k-step kt + 2 go out while kt
+  // is computed, so a load has two k-steps to land.
+  constexpr int NST = 3 * STAGE <= 160 * 1024 ? 3 : 2;
+  // Every wave issues the same number of loads per stage (the last ones
+  // repeat a piece of its own: the same bytes to the same place), so the
+  // wait for a stage is one immediate count.
+  constexpr int NPW = (PIECES + 7) / 8;
+  static_assert(2 * STAGE <= 160 * 1024, "two stages must fit LDS");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[NST * STAGE];
+
+  const int tiles_m = (int)((g.m + BM - 1) / BM);
+  const int tiles_n = (int)((g.n + BN - 1) / BN);
+  int tm, tn;
+  slice_tile_coords(tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: one buffer resource per load
+  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+  const int fr = lane & 31, fg = lane >> 5;
+
+  const int64_t nk = g.kp * ES / RB;
+  const int64_t run = nk * TILE;  // bytes of one 64-row tile's k-run
+  const unsigned char* ga = static_cast<const unsigned char*>(g.a) + (int64_t)(2 * tm) * run;
+  const unsigned char* gb = static_cast<const unsigned char*>(g.b) + (int64_t)tn * run;
+  const int64_t sa = g.slice_stride_a * ES, sb = g.slice_stride_b * ES;
+  const int nrec_a = (int)(uint32_t)(2 * run), nrec_b = (int)(uint32_t)run;  // num_records is unsigned
+  // 1 KB piece p of a stage: A slice p / 4, quarter p % 4 (64-row tile
+  // (p % 4) / 2, half p % 2); then B slice (p - 4S) / 2, half p % 2.
+  auto dma = [&](int p, int64_t kt, int st) {
+    const unsigned char* base;
+    int nrec, voff, loff;
+    if (p < 4 * S) {
+      const int sl = p >> 2, q = p & 3;
+      base = ga + sl * sa;
+      nrec = nrec_a;
+      voff = (int)((q >> 1) * run) + (q & 1) * 1024 + lane * 16;
+      loff = sl * A_SLICE + q * 1024;
+    } else {
+      const int pb = p - 4 * S, sl = pb >> 1;
+      base = gb + sl * sb;
+      nrec = nrec_b;
+      voff = (pb & 1) * 1024 + lane * 16;
+      loff = A_BYTES + sl * B_SLICE + (pb & 1) * 1024;
+    }
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, nrec, 0x00020000);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_ptr)(lds + st * STAGE + loff), 16, voff,
+                                             (int)(kt * TILE), 0, 0);
+  };
+  auto piece = [&](int i) {
+    const int p = wave + 8 * i;
+    return p < PIECES ? p : wave;
+  };
+  auto frag = [&](const unsigned char* tile, int row) {
+    return *reinterpret_cast<const frag_t*>(tile + row * RB + swz_chunk32(row, fg) * 16);
+  };
+
+  double acc[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0;
+
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) dma(piece(i), 0, 0);
+  if constexpr (NST == 3) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) dma(piece(i), nk > 1 ? 1 : 0, 1);
+    wait_vm<NPW>();
+  } else {
+    wait_vm<0>();
+  }
+  block_sync();
+  for (int64_t k0 = 0; k0 < nk; k0 += g.kflush) {
+    const int64_t k1 = min(nk, k0 + (int64_t)g.kflush);
+    acc_t lvl[S];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) lvl[d][v] = 0;
+    for (int64_t kt = k0; kt < k1; ++kt) {
+      const int st = (int)(kt % NST);
+      const int sn = NST == 3 ? (st == 0 ? 2 : st - 1) : (st ^ 1);  // stage of k-step kt + NST - 1
+      // Past the end the last k-step is reloaded into a stage nobody reads.
+      const int64_t knext = kt + NST - 1 < nk ? kt + NST - 1 : nk - 1;
+      const unsigned char* ta = lds + st * STAGE;
+      const unsigned char* tb = ta + A_BYTES;
+      frag_t fb[S];
+#pragma unroll
+      for (int t = 0; t < S; ++t) fb[t] = frag(tb + t * B_SLICE, wn0 + fr);
+      frag_t fa = frag(ta, wm0 + fr);
+      int q = 0;  // loads of k-step kt + NST - 1 issued so far
+#pragma unroll
+      for (int s = 1; s <= S; ++s) {
+        frag_t fa_next = fa;
+        if (s < S) fa_next = frag(ta + s * A_SLICE, wm0 + fr);
+#pragma unroll
+        for (int t = 1; t <= S + 1 - s; ++t) {
+          lvl[s + t - 2] = Tr::mfma(fa, fb[t - 1], lvl[s + t - 2]);
+          if (q < NPW) {
+            dma(piece(q), knext, sn);
+            ++q;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        fa = fa_next;
+      }
+      for (; q < NPW; ++q) dma(piece(q), knext, sn);
+      // Stage kt + 1 is complete once at most this k-step's loads are out.
+      wait_vm<NST == 3 ? NPW : 0>();
+      block_sync();
+    }
+#pragma unroll
+    for (int d = 2; d <= S + 1; ++d) {
+      const double sc = pow2neg(BETA * d);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = __builtin_fma((double)lvl[d - 2][v], sc, acc[v]);
+    }
+  }
+  // No load may still be writing this block's LDS when it ends.
+  wait_vm<0>();
+
+  store_tile32(g, acc, m0 + wm0, n0 + wn0, lane);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <int ET, int S>
@@ -724,7 +952,8 @@ static hipError_t launch_split_s(const SplitArgs& a, int* exps, void* out, hipSt
 //              every k-step;
 //   variant 2: as variant 1, with the level sums kept across k-steps and
 //              flushed to FP64 every slice_flush_steps k-steps;
-//   variant 3: slice_gemm_dma (BF16, INT8).
+//   variant 3: slice_gemm_dma (BF16, INT8);
+//   variant 4: slice_gemm_x32 (BF16, INT8).
 template <int ET, int S, int V>
 static hipError_t launch_slice_v(const SliceGemmArgs& g, hipStream_t st) {
   typedef SliceTraits<ET> Tr;
@@ -746,13 +975,14 @@ static hipError_t launch_slice_v(const SliceGemmArgs& g, hipStream_t st) {
 int default_slice_variant(int et, int S) { return et != 1 ? 3 : (S <= 8 ? 0 : 2); }
 
 int resolve_slice_variant(int et, int S, int variant) {
-  if (variant < 0 || variant > 3) return default_slice_variant(et, S);
-  if (variant == 3 && et == 1) return default_slice_variant(et, S);
+  if (variant < 0 || variant > 4) return default_slice_variant(et, S);
+  if (variant >= 3 && et == 1) return default_slice_variant(et, S);
+  if (variant == 4 && S > 8) return 3;  // the 32 x 32 shape is built up to 8 slices
   if (variant == 0 && S > (et == 1 ? 8 : 6)) return default_slice_variant(et, S);
   return variant;
 }
 
-bool slice_variant_tiled(int variant) { return variant == 3; }
+int slice_variant_tiled(int variant) { return variant == 3 ? 1 : (variant == 4 ? 2 : 0); }
 
 template <int ET, int S>
 static hipError_t launch_slice_s(const SliceGemmArgs& g, int variant, hipStream_t st) {
@@ -762,6 +992,17 @@ static hipError_t launch_slice_s(const SliceGemmArgs& g, int variant, hipStream_
     else return hipErrorInvalidValue;
   }
   if (variant == 2) return launch_slice_v<ET, S, 2>(g, st);
+  if (variant == 4) {
+    if constexpr (ET != 1 && S <= 8) {
+      const int64_t tiles = ((g.m + 127) / 128) * ((g.n + 63) / 64);
+      if (tiles <= 0) return hipSuccess;
+      if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((slice_gemm_x32<ET, S>), dim3((unsigned)tiles), dim3(512), 0, st, g);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (variant == 3) {
     if constexpr (ET != 1) {
       const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);

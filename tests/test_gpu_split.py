@@ -49,7 +49,7 @@ def test_integer_bit_exact(bq, kind, S):
     assert np.array_equal(run(bq, A, B, kind, S), oracle.gemm(A, B))
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
 @pytest.mark.parametrize("kind,S", [("bf16", 3), ("bf16", 6), ("bf16", 8), ("fp8", 5), ("fp8", 9),
                                     ("fp8", 13), ("int8", 4), ("int8", 7), ("int8", 9)])
 def test_matches_cpu_split_model(bq, kind, S, variant, monkeypatch):
@@ -58,8 +58,10 @@ def test_matches_cpu_split_model(bq, kind, S, variant, monkeypatch):
     split model; ragged shape."""
     if variant == "0" and S > (8 if kind == "fp8" else 6):
         pytest.skip("8-wave shape not built for this many slices")
-    if variant == "3" and kind == "fp8":
-        pytest.skip("direct-to-LDS shape is built for 16-byte digit chunks (BF16, INT8)")
+    if variant in ("3", "4") and kind == "fp8":
+        pytest.skip("direct-to-LDS shapes are built for 16-byte digit chunks (BF16, INT8)")
+    if variant == "4" and S > 8:
+        pytest.skip("the 32 x 32 shape is built up to 8 slices")
     monkeypatch.setenv("BQ_SLICE_VARIANT", variant)
     A, B = inputs.pair(130, 100, 70, "uniform", seed=13)
     print(f"split {kind} S={S} variant {variant} vs model", flush=True)
@@ -68,14 +70,14 @@ def test_matches_cpu_split_model(bq, kind, S, variant, monkeypatch):
     assert oracle.rel_frobenius(got, ref) <= 1e-14
 
 
-@pytest.mark.parametrize("variant", ["2", "3"])
+@pytest.mark.parametrize("variant", ["2", "3", "4"])
 @pytest.mark.parametrize("flush", ["1", "3"])
 @pytest.mark.parametrize("kind,S", [("bf16", 8), ("fp8", 9), ("int8", 8)])
 def test_level_flush_interval(bq, kind, S, flush, variant, monkeypatch):
     """Level sums kept across k-steps and flushed every 1 or 3 k-steps (K =
     700: several flushes and a partial last interval) against the model."""
-    if variant == "3" and kind == "fp8":
-        pytest.skip("direct-to-LDS shape is built for BF16 and INT8")
+    if variant in ("3", "4") and kind == "fp8":
+        pytest.skip("direct-to-LDS shapes are built for BF16 and INT8")
     monkeypatch.setenv("BQ_SLICE_VARIANT", variant)
     monkeypatch.setenv("BQ_SLICE_FLUSH", flush)
     A, B = inputs.pair(40, 700, 36, "logspread", seed=16)
