@@ -146,6 +146,41 @@ def heev_leg(bq, inputs, torch, n, log):
     return out
 
 
+def ops_leg(bq, inputs, torch, n, log):
+    """The 16 op pairs (N, T, C, H for each operand; the paper averages its
+    multiplication timings over them) on one uniform n x n product: per pair
+    the median of 3 timed calls, then the mean over pairs and the worst pair
+    against N x N."""
+    A = inputs.device_uniform(n, n, 71, "cuda")
+    B = inputs.device_uniform(n, n, 72, "cuda")
+    C = torch.empty_like(A)
+    res, _ = bq.workspace_size(n, n, n)
+    ws = torch.empty(res, dtype=torch.uint8, device="cuda")
+    flop_eff = 64 * 2.0 * n ** 3
+    per = {}
+    for oa in "NTCH":
+        for ob in "NTCH":
+            bq.bq_gemm(A, B, C, opA=oa, opB=ob, workspace=ws)
+            ts = []
+            for _ in range(3):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                bq.bq_gemm(A, B, C, opA=oa, opB=ob, workspace=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            per[oa + ob] = sorted(ts)[1]
+    mean = sum(per.values()) / len(per)
+    out = {"workload": f"uniform[-1,1] biquaternion product n={n}, all 16 op pairs", "ms": {k: round(v, 2) for k, v in per.items()},
+           "mean_ms": round(mean, 2), "mean_eff_tflops": round(flop_eff / (mean * 1e-3) / 1e12, 2),
+           "worst_vs_NN": round(max(per.values()) / per["NN"], 3)}
+    log(f"ops: mean {mean:.1f} ms over 16 pairs, NN {per['NN']:.1f} ms, worst/NN {out['worst_vs_NN']}")
+    del A, B, C, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(bq, inputs, torch, count, log):
     """count products, square sizes log-uniform over 64..1536 (seed 5),
     uniform[-1, 1]: one grouped plan (graph of a pre-combination launch and
@@ -213,6 +248,8 @@ def main():
                     help="rows/cols of the sub-block the oracle recomputes (0: skip)")
     ap.add_argument("--split", default="split_int8,split_bf16,split_fp8",
                     help="split-precision forms timed beside FP64 on the same inputs ('' to skip)")
+    ap.add_argument("--ops-n", type=int, default=4096,
+                    help="n of the all-op-pairs leg (0 to skip)")
     ap.add_argument("--heev", type=int, default=4096,
                     help="n of the diagonalization leg (complex order 2n; 0 to skip)")
     ap.add_argument("--batched", type=int, default=512,
@@ -383,9 +420,12 @@ def main():
 
     batched = None
     heev = None
-    if args.batched > 0 or args.heev > 0:
+    ops = None
+    if args.batched > 0 or args.heev > 0 or args.ops_n > 0:
         del A, B, C
         torch.cuda.empty_cache()
+    if args.ops_n > 0:
+        ops = ops_leg(bq, inputs, torch, args.ops_n, log)
     if args.batched > 0:
         batched = batched_leg(bq, inputs, torch, args.batched, log)
     if args.heev > 0:
@@ -404,7 +444,7 @@ def main():
            "mfma_frac_of_fp64_peak": round(exec_tflops / PEAK_FP64_TFLOPS, 4),
            "rel_err_sampled_vs_oracle": rel_err,
            "roofline": roofline, "combine": combine, "cpu_baseline": cpu,
-           "split_precision": split, "batched": batched, "diagonalization": heev}
+           "split_precision": split, "op_pairs": ops, "batched": batched, "diagonalization": heev}
     print(json.dumps(out), flush=True)
 
 

@@ -139,3 +139,32 @@ def test_empty(bq):
     w, V, info = bq.heev(A)
     torch.cuda.synchronize()
     assert w.numel() == 0 and int(info.item()) == 0
+
+
+@pytest.mark.parametrize("case", ["full", "anti_j", "blocks"])
+def test_strided_input_and_output(bq, case):
+    """A with ld > n (a column slice of a wider buffer) and V with ldv > 2n:
+    the padding of V is left alone."""
+    import ctypes
+
+    import torch
+
+    from paper_2609_02081_amd import _binding as B
+
+    n, mask = 45, CASES[case]
+    A = inputs.hermitian_random(n, mask, seed=55)
+    buf = torch.zeros((8, n, n + 7), dtype=torch.float64, device="cuda")
+    buf[:, :, :n] = torch.from_numpy(A).to("cuda")
+    Am = B.matrix(buf[:, :, :n], mask)
+    ldv = 2 * n + 5
+    Vt = torch.full((2 * n, ldv), 9.0 + 0j, dtype=torch.complex128, device="cuda")  # column-major V, ldv
+    w = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    need = B.heev_workspace_size(n, mask, True)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    B.check(B.lib().bq_heev(B.handle(0), ctypes.byref(Am), ctypes.c_void_p(w.data_ptr()),
+                            ctypes.c_void_p(Vt.data_ptr()), ldv, None, ctypes.c_void_p(ws.data_ptr()), need,
+                            B._stream(None)))
+    torch.cuda.synchronize()
+    Vfull = Vt.cpu().numpy()
+    assert np.all(Vfull[:, 2 * n:] == 9.0)
+    check(A, w.cpu().numpy(), Vfull[:, :2 * n].T)
