@@ -66,13 +66,26 @@ typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
  * slices + 1, and accumulate and rescale in FP64.  Digit types: BF16
  * (beta 7, slices 1..8, default 7), OCP FP8 E4M3 (beta 4, slices 1..14,
  * default 13), INT8 (beta 7 with one bit of exponent headroom, so the
- * leading digit fits a signed byte; slices 1..9, default 7).  The Hadamard and
- * Gauss pre-combinations and the post-combination stay FP64. */
+ * leading digit fits a signed byte; slices 1..9, default 7).
+ * SPLIT_INT8_CRT is the integer-modular form (Ozaki scheme II): every row of
+ * the left factor (column of the right) is scaled by a power of two to b-bit
+ * integers (b <= 53, one rounding per element), the exact integer product is
+ * carried as `slices` residues modulo the fixed odd pairwise coprime moduli
+ * 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191,
+ * 181, 179, 173, 167, 163 (first `slices` of them), one exact INT8 GEMM with
+ * int32 sums per modulus, and recovered by the Chinese remainder theorem in
+ * mixed radix with an FP64 evaluation.  b is the largest value <= 53 with
+ * p_1 ... p_N > 2 k 2^(2b); slices 1..20, 0 = the fewest moduli that give
+ * b = 53 for the call's k (16 at k = 16384), and an explicit count that gives
+ * b = 0 is BQ_ERR_INVALID_VALUE.  k is limited to 133120 (int32 sums stay
+ * exact).  The Hadamard and Gauss pre-combinations and the post-combination
+ * stay FP64. */
 typedef enum {
   BQ_PREC_FP64 = 0,
   BQ_PREC_SPLIT_BF16 = 1,
   BQ_PREC_SPLIT_FP8 = 2,
-  BQ_PREC_SPLIT_INT8 = 3
+  BQ_PREC_SPLIT_INT8 = 3,
+  BQ_PREC_SPLIT_INT8_CRT = 4
 } bq_prec_t;
 
 typedef struct bq_handle_s* bq_handle_t;
@@ -247,6 +260,10 @@ typedef enum {
                                flops = pairs * 2 m n k, config = slices */
   BQ_KERNEL_GROUPED = 14,    /* one launch of a batched plan (whole graph);
                                flops = executed real-GEMM flops of all problems */
+  BQ_KERNEL_CRT_GEMM = 15,   /* the INT8 GEMMs of one real product in the CRT
+                               form; flops = moduli * 2 m n k, config = moduli */
+  BQ_KERNEL_CRT_COMBINE = 16, /* residues -> FP64 product -> targets; bytes
+                               read + written */
   BQ_KERNEL_HEEV_MAP = 20,   /* isomorph (or reduced block) of a Hermitian
                                biquaternion; bytes read + written */
   BQ_KERNEL_HEEV_SOLVE = 21, /* one complex Hermitian eigensolve (zheevd);

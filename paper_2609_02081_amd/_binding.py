@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbq.so")
 
 OPS = {"N": 0, "T": 1, "C": 2, "H": 3}
-PRECS = {"fp64": 0, "split_bf16": 1, "split_fp8": 2, "split_int8": 3}
+PRECS = {"fp64": 0, "split_bf16": 1, "split_fp8": 2, "split_int8": 3, "split_int8_crt": 4}
 STATUS = {0: "BQ_OK", 1: "BQ_ERR_INVALID_VALUE", 2: "BQ_ERR_UNSUPPORTED", 3: "BQ_ERR_ALIAS",
           4: "BQ_ERR_WORKSPACE", 5: "BQ_ERR_HIP", 6: "BQ_ERR_ARCH"}
 
@@ -36,7 +36,8 @@ class BqTraceRecord(ctypes.Structure):
 
 
 KERNEL_NAMES = {0: "gemm_gauss", 1: "gemm_rc", 2: "gemm_cr", 3: "gemm_rr", 10: "combine", 11: "fill",
-                12: "split", 13: "slice_gemm", 14: "grouped", 20: "heev_map", 21: "heev_solve",
+                12: "split", 13: "slice_gemm", 14: "grouped", 15: "crt_gemm",
+                16: "crt_combine", 20: "heev_map", 21: "heev_solve",
                 22: "heev_assemble"}
 
 
@@ -145,6 +146,13 @@ def matrix(X, mask: int = FULL, rows=None, cols=None) -> BqMatrix:
         return M
     M.rows, M.cols = ref.shape
     M.ld = ref.stride(0) if ref.shape[0] > 1 else max(1, ref.shape[1])
+    if ref.numel() == 0:
+        # nothing is read or written: the layout does not matter
+        M.ld = max(1, ref.shape[1])
+        for c, t in enumerate(comps):
+            present = t is not None and (mask >> c & 1) and t.data_ptr() != 0
+            M.comp[c] = t.data_ptr() if present else None
+        return M
     for c, t in enumerate(comps):
         if t is None or not (mask >> c & 1):
             M.comp[c] = None

@@ -210,7 +210,8 @@ size_t combo_slot_bytes(int64_t rows, int64_t cols) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Arithmetic of the real GEMMs: et = -1 FP64 MFMA, else the digit type of
-// the split form (0 BF16, 1 FP8, 2 INT8) with S slices.
+// the split form (0 BF16, 1 FP8, 2 INT8) with S slices, or 3 for the CRT
+// form with S moduli (S = 0: chosen from k by crt_default_moduli).
 struct Prec {
   int et = -1;
   int S = 0;
@@ -220,23 +221,80 @@ constexpr int kDefaultSlices[3] = {7, 13, 7};
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// CRT form: prod(p_1..p_N) > k 2^(2b + 1), exactly (32-bit limbs), i.e. the
+// moduli tell apart every integer of |P| <= k 2^(2b) with |P| < M / 2.
+bool crt_carries(int N, int64_t k, int b) {
+  std::vector<uint64_t> P{1};
+  for (int i = 0; i < N; ++i) {
+    uint64_t carry = 0;
+    for (uint64_t& l : P) {
+      const uint64_t t = l * uint64_t(bq::crt_modulus(i)) + carry;
+      l = t & 0xffffffffu;
+      carry = t >> 32;
+    }
+    if (carry) P.push_back(carry);
+  }
+  const int sh = 2 * b + 1;
+  std::vector<uint64_t> R(size_t(sh / 32 + 3), 0);
+  const unsigned __int128 v = (unsigned __int128)uint64_t(k) << (sh % 32);
+  R[sh / 32] = uint64_t(v) & 0xffffffffu;
+  R[sh / 32 + 1] = uint64_t(v >> 32) & 0xffffffffu;
+  R[sh / 32 + 2] = uint64_t(v >> 64) & 0xffffffffu;
+  const size_t L = std::max(P.size(), R.size());
+  for (size_t i = L; i-- > 0;) {
+    const uint64_t a = i < P.size() ? P[i] : 0, c = i < R.size() ? R[i] : 0;
+    if (a != c) return a > c;
+  }
+  return false;
+}
+
+// Integer bits b of the CRT form: the largest b <= 53 the N moduli carry for
+// inner dimension k (0 if none).
+int crt_bits(int N, int64_t k) {
+  k = std::max<int64_t>(k, 1);
+  double logm = 0.0;
+  for (int i = 0; i < N; ++i) logm += std::log2(double(bq::crt_modulus(i)));
+  int b = std::min(53, int(std::floor((logm - 1.0 - std::log2(double(k))) / 2.0)) + 1);
+  while (b > 0 && !crt_carries(N, k, b)) --b;
+  return std::max(b, 0);
+}
+
+// Fewest moduli that carry 53 bits for inner dimension k.
+int crt_default_moduli(int64_t k) {
+  for (int N = 1; N <= bq::kMaxCrtModuli; ++N)
+    if (crt_bits(N, k) >= 53) return N;
+  return bq::kMaxCrtModuli;
+}
+
+// Slices (moduli) one real product of inner dimension k uses.
+int split_count(const Prec& pr, int64_t k) {
+  return (pr.et == 3 && pr.S == 0) ? crt_default_moduli(k) : pr.S;
+}
+
+// Largest padded k of the CRT GEMM: k * 127^2 < 2^31 keeps int32 sums exact.
+constexpr int64_t kCrtMaxK = 133120;
+
 // Digit buffers of one split real product (reused by every real product).
+// The CRT form adds the residue planes of the product, N x m x n bytes.
 struct SplitLayout {
   int64_t rows_pad, cols_pad, kp;
-  size_t a_bytes, b_bytes, ea_bytes, eb_bytes;
-  size_t total() const { return a_bytes + b_bytes + ea_bytes + eb_bytes; }
+  int S;
+  size_t a_bytes, b_bytes, ea_bytes, eb_bytes, r_bytes;
+  size_t total() const { return a_bytes + b_bytes + ea_bytes + eb_bytes + r_bytes; }
 };
 
 SplitLayout split_layout(const Prec& pr, int64_t m, int64_t n, int64_t k) {
   SplitLayout L{};
   const int es = pr.et == 0 ? 2 : 1;
+  L.S = split_count(pr, k);
   L.rows_pad = round_up(m, 128);
-  L.cols_pad = round_up(n, 64);
+  L.cols_pad = round_up(n, pr.et == 3 ? 128 : 64);
   L.kp = round_up(k, 64);
-  L.a_bytes = align256(size_t(pr.S) * size_t(L.rows_pad) * size_t(L.kp) * es);
-  L.b_bytes = align256(size_t(pr.S) * size_t(L.cols_pad) * size_t(L.kp) * es);
+  L.a_bytes = align256(size_t(L.S) * size_t(L.rows_pad) * size_t(L.kp) * es);
+  L.b_bytes = align256(size_t(L.S) * size_t(L.cols_pad) * size_t(L.kp) * es);
   L.ea_bytes = align256(size_t(L.rows_pad) * 4);
   L.eb_bytes = align256(size_t(L.cols_pad) * 4);
+  L.r_bytes = pr.et == 3 ? align256(size_t(L.S) * size_t(m) * size_t(n)) : 0;
   return L;
 }
 
@@ -268,10 +326,15 @@ bq_status_t prec_of(bq_prec_t prec, int slices, Prec* out) {
     case BQ_PREC_SPLIT_BF16: p.et = 0; break;
     case BQ_PREC_SPLIT_FP8: p.et = 1; break;
     case BQ_PREC_SPLIT_INT8: p.et = 2; break;
+    case BQ_PREC_SPLIT_INT8_CRT: p.et = 3; break;
     default: return fail(BQ_ERR_INVALID_VALUE, "unknown precision");
   }
   if (slices < 0) return fail(BQ_ERR_INVALID_VALUE, "slices must be >= 0");
-  if (p.et >= 0) {
+  if (p.et == 3) {
+    if (slices > bq::kMaxCrtModuli)
+      return fail(BQ_ERR_INVALID_VALUE, "moduli above " + std::to_string(bq::kMaxCrtModuli));
+    p.S = slices;
+  } else if (p.et >= 0) {
     p.S = slices == 0 ? kDefaultSlices[p.et] : slices;
     if (p.S > bq::max_slices(p.et))
       return fail(BQ_ERR_INVALID_VALUE, "slices above " + std::to_string(bq::max_slices(p.et)) +
@@ -343,6 +406,12 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
   const int64_t kb = op_trans(opB) ? B->cols : B->rows, n = op_trans(opB) ? B->rows : B->cols;
   if (k != kb) return fail(BQ_ERR_INVALID_VALUE, "inner dimensions of op(A) and op(B) differ");
   if (C->rows != m || C->cols != n) return fail(BQ_ERR_INVALID_VALUE, "C must be rows(op(A)) x cols(op(B))");
+  if (pr.et == 3 && k > 0) {
+    if (round_up(k, 64) > kCrtMaxK)
+      return fail(BQ_ERR_UNSUPPORTED, "CRT form: k above " + std::to_string(kCrtMaxK) + " is not supported");
+    if (crt_bits(split_count(pr, k), k) < 1)
+      return fail(BQ_ERR_INVALID_VALUE, "CRT form: too few moduli for this inner dimension");
+  }
   if (C->rows > 0 && C->cols > 0)
     for (int c = 0; c < 8; ++c)
       if ((out_mask >> c & 1) && !C->comp[c])
@@ -492,16 +561,20 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   void* dig_b = nullptr;
   int* exp_a = nullptr;
   int* exp_b = nullptr;
+  signed char* res_planes = nullptr;
   if (pr.et >= 0 && k > 0) {
     sl = split_layout(pr, m, n, k);
     dig_a = wp; wp += sl.a_bytes;
     dig_b = wp; wp += sl.b_bytes;
     exp_a = reinterpret_cast<int*>(wp); wp += sl.ea_bytes;
     exp_b = reinterpret_cast<int*>(wp); wp += sl.eb_bytes;
+    res_planes = reinterpret_cast<signed char*>(wp); wp += sl.r_bytes;
   }
+  const bool crt = pr.et == 3;
   const int es = pr.et == 0 ? 2 : 1;
-  const int beta = pr.et >= 0 ? bq::slice_beta(pr.et) : 0;
-  const int head = pr.et >= 0 ? bq::slice_head(pr.et) : 0;
+  const int S = sl.S;  // slices, or moduli of the CRT form, for this k
+  const int beta = crt ? crt_bits(S, k) : (pr.et >= 0 ? bq::slice_beta(pr.et) : 0);
+  const int head = (pr.et >= 0 && !crt) ? bq::slice_head(pr.et) : 0;
 
   // One real product T = X Y of the split form, X = xw1 x1 + xw2 x2 (m x k),
   // Y = yw1 y1 + yw2 y2 (k x n); C_w op= cw * T for each (w, cw).
@@ -518,8 +591,8 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       ++sg.ntgt;
     }
     if (sg.ntgt == 0) return hipSuccess;
-    const int variant = bq::resolve_slice_variant(pr.et, pr.S, slice_variant());
-    const int tiled = bq::slice_variant_tiled(variant);
+    const int variant = crt ? 0 : bq::resolve_slice_variant(pr.et, S, slice_variant());
+    const int tiled = crt ? 1 : bq::slice_variant_tiled(variant);
     // The left factor takes one exponent per row of op(A): along the stored
     // rows (row kernels) for N and C, along the stored columns (column
     // kernels, which also transpose the digits) for T and H; the right factor
@@ -535,17 +608,53 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     const double elems_x = double(m) * double(k), elems_y = double(k) * double(n);
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
-                elems_x * 8.0 * (x2 ? 2 : 1) * 2.0 + double(sl.rows_pad) * double(sl.kp) * pr.S * es);
-      hipError_t e = bq::launch_split(pr.et, pr.S, xa, exp_a, dig_a, s);
+                elems_x * 8.0 * (x2 ? 2 : 1) * 2.0 + double(sl.rows_pad) * double(sl.kp) * S * es);
+      hipError_t e = crt ? bq::launch_crt_split(S, xa, exp_a, dig_a, s)
+                         : bq::launch_split(pr.et, S, xa, exp_a, dig_a, s);
       tr.done();
       if (e != hipSuccess) return e;
     }
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, k, n, 0, 0.0,
-                elems_y * 8.0 * (y2 ? 2 : 1) * 2.0 + double(sl.cols_pad) * double(sl.kp) * pr.S * es);
-      hipError_t e = bq::launch_split(pr.et, pr.S, ya, exp_b, dig_b, s);
+                elems_y * 8.0 * (y2 ? 2 : 1) * 2.0 + double(sl.cols_pad) * double(sl.kp) * S * es);
+      hipError_t e = crt ? bq::launch_crt_split(S, ya, exp_b, dig_b, s)
+                         : bq::launch_split(pr.et, S, ya, exp_b, dig_b, s);
       tr.done();
       if (e != hipSuccess) return e;
+    }
+    if (crt) {
+      // One exact INT8 GEMM per modulus into residue planes, then the
+      // Chinese remainder reconstruction and the targets.
+      const bq::CrtGemmArgs cg{dig_a, dig_b, sl.rows_pad * sl.kp, sl.cols_pad * sl.kp, sl.kp, m, n,
+                               res_planes, m * n, n};
+      {
+        Tracer tr(h, s, BQ_KERNEL_CRT_GEMM, S, m, n, k, double(S) * 2.0 * double(m) * double(n) * double(k), 0.0);
+        hipError_t e = bq::launch_crt_gemm(S, cg, s);
+        tr.done();
+        if (e != hipSuccess) return e;
+      }
+      bq::CrtCombineArgs cc{};
+      cc.res = res_planes;
+      cc.plane_r = m * n;
+      cc.ldr = n;
+      cc.ea = exp_a;
+      cc.eb = exp_b;
+      cc.m = m;
+      cc.n = n;
+      cc.bits = beta;
+      cc.ntgt = sg.ntgt;
+      int rw = 0;
+      for (int q = 0; q < sg.ntgt; ++q) {
+        cc.c[q] = sg.c[q];
+        cc.coef[q] = sg.coef[q];
+        cc.mode[q] = sg.mode[q];
+        rw += sg.mode[q] == bq::TGT_ACCUM ? 2 : 1;
+      }
+      cc.ldc = C->ld;
+      Tracer tr(h, s, BQ_KERNEL_CRT_COMBINE, S, m, n, 0, 0.0, double(m) * double(n) * (double(S) + 8.0 * rw));
+      hipError_t e = bq::launch_crt_combine(S, cc, s);
+      tr.done();
+      return e;
     }
     sg.a = dig_a;
     sg.b = dig_b;
@@ -557,11 +666,11 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     sg.m = m;
     sg.n = n;
     sg.beta = beta;
-    sg.kflush = slice_flush(pr.et, pr.S);
+    sg.kflush = slice_flush(pr.et, S);
     sg.ldc = C->ld;
-    const double pairs = double(pr.S) * double(pr.S + 1) / 2.0;
-    Tracer tr(h, s, BQ_KERNEL_SLICE_GEMM, pr.S, m, n, k, pairs * 2.0 * double(m) * double(n) * double(k), 0.0);
-    hipError_t e = bq::launch_slice_gemm(pr.et, pr.S, variant, sg, s);
+    const double pairs = double(S) * double(S + 1) / 2.0;
+    Tracer tr(h, s, BQ_KERNEL_SLICE_GEMM, S, m, n, k, pairs * 2.0 * double(m) * double(n) * double(k), 0.0);
+    hipError_t e = bq::launch_slice_gemm(pr.et, S, variant, sg, s);
     tr.done();
     return e;
   };

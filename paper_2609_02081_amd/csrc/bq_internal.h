@@ -113,6 +113,35 @@ struct GroupedItem {
   int tm, tn;
 };
 
+// CRT-based split form (bq_split.hip): residue planes and their GEMMs.
+constexpr int kMaxCrtModuli = 20;
+struct CrtGemmArgs {
+  const void* a;  // residues of X: [N][rows_pad (128)][kp], tiled 64-byte layout
+  const void* b;  // residues of Y: [N][cols_pad (128)][kp], same
+  int64_t plane_a, plane_b;  // bytes between modulus planes
+  int64_t kp;
+  int64_t m, n;
+  signed char* out;  // result residues [N][m][ldr]
+  int64_t plane_r, ldr;
+};
+struct CrtCombineArgs {
+  const signed char* res;
+  int64_t plane_r, ldr;
+  const int* ea;
+  const int* eb;
+  int64_t m, n;
+  int bits;
+  int ntgt;
+  double* c[kMaxSliceTargets];
+  double coef[kMaxSliceTargets];
+  int mode[kMaxSliceTargets];
+  int64_t ldc;
+  // Filled by the launcher: Chinese remainder constants of the N moduli.
+  uint32_t cl[kMaxCrtModuli][4];  // c_i modulo 2^128, 32-bit limbs, low first
+  double frac[kMaxCrtModuli];     // c_i / M
+  uint32_t ml[4];                 // M modulo 2^128
+};
+
 // Complex linear map of the 8 components into an R x R complex buffer
 // (heev_map_kernel): quadrant q (R = 2n: 0..3 = 11, 12, 21, 22; R = n: 0).
 struct HeevMapArgs {
@@ -167,6 +196,10 @@ int slice_kstep(int et);              // k per MFMA step (32 or 64)
 int slice_beta(int et);
 int slice_head(int et);
 int slice_flush_steps(int et, int S);  // k-steps per exact level accumulation
+hipError_t launch_crt_split(int N, const SplitArgs& a, int* exps, void* out, hipStream_t s);  // a.beta = bits
+hipError_t launch_crt_gemm(int N, const CrtGemmArgs& g, hipStream_t s);
+hipError_t launch_crt_combine(int N, const CrtCombineArgs& g, hipStream_t s);
+int crt_modulus(int i);
 // Hermitian eigenproblem kernels (bq_heev.hip).
 hipError_t launch_heev_map(const HeevMapArgs& a, hipStream_t s);
 hipError_t launch_heev_merge(const double* x1, int64_t n1, const double* x2, int64_t n2, double s2, int rev,

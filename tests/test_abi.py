@@ -194,3 +194,43 @@ def test_create_without_gpu_fails_cleanly():
     h = ctypes.c_void_p()
     assert B.lib().bq_create(ctypes.byref(h), 0) != OK
     assert not h.value
+
+
+@pytest.mark.parametrize("k", [1, 40, 1000, 16384, 70000, 133120])
+def test_crt_workspace_uses_oracle_moduli(k):
+    """CRT form: digits are one byte per modulus (rows and columns padded to
+    128, k to 64), plus N residue planes of m x n bytes; N = 0 resolves to
+    the fewest moduli that carry 53 bits for this k, the count the oracle
+    (which checks the modulus product with exact integers) picks."""
+    from oracle import ozaki2
+
+    m, n = 100, 60
+    res, mn = ws_need(m, n, k)
+    N = ozaki2.default_moduli(k)
+    al = lambda x: (x + 255) // 256 * 256
+    kp = (k + 63) // 64 * 64
+    extra = al(N * 128 * kp) + al(N * 128 * kp) + al(128 * 4) + al(128 * 4) + al(N * m * n)
+    assert B.workspace_size(m, n, k, 0xFF, 0xFF, "split_int8_crt", 0) == (res + extra, mn + extra)
+    N2 = max(1, N - 3)
+    extra2 = al(N2 * 128 * kp) * 2 + al(128 * 4) * 2 + al(N2 * m * n)
+    assert B.workspace_size(m, n, k, 0xFF, 0xFF, "split_int8_crt", N2) == (res + extra2, mn + extra2)
+
+
+def test_crt_limits():
+    from oracle import ozaki2
+
+    ws = dict(ws=4 * FAKE, ws_bytes=1 << 40)
+    crt = B.PRECS["split_int8_crt"]
+
+    def chk(k, slices=0):
+        return check(mat(8, k, FAKE), mat(k, 8, 2 * FAKE), mat(8, 8, 3 * FAKE), prec=crt, slices=slices, **ws)
+
+    assert chk(133120) == OK
+    assert chk(133121) == UNSUPPORTED          # int32 sums of 127^2 products would overflow
+    assert chk(64, slices=21) == INVALID       # 20 moduli at most
+    for k in (1, 64, 5000):
+        # the smallest count that still carries one bit passes, one fewer fails
+        n_min = next(N for N in range(1, 21) if ozaki2.bits_for(N, k) >= 1)
+        assert chk(k, slices=n_min) == OK
+        if n_min > 1:
+            assert chk(k, slices=n_min - 1) == INVALID
