@@ -246,7 +246,7 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="rows/cols of the sub-block the oracle recomputes (0: skip)")
-    ap.add_argument("--split", default="split_int8,split_bf16,split_fp8",
+    ap.add_argument("--split", default="split_int8_crt,split_int8,split_bf16,split_fp8",
                     help="split-precision forms timed beside FP64 on the same inputs ('' to skip)")
     ap.add_argument("--ops-n", type=int, default=4096,
                     help="n of the all-op-pairs leg (0 to skip)")
@@ -353,9 +353,10 @@ def main():
         torch.cuda.empty_cache()
         # Slice count: start at the library default and add slices until the
         # sampled result agrees with the FP64 result (itself ~1e-14 from the
-        # oracle) to 5e-13; the error reported is then the oracle's.
-        max_s = {"split_bf16": 8, "split_fp8": 14, "split_int8": 9}
-        start_s = {"split_bf16": 7, "split_fp8": 13, "split_int8": 7}
+        # oracle) to 5e-13; the error reported is then the oracle's.  The CRT
+        # form runs once at its default (the fewest moduli carrying 53 bits).
+        max_s = {"split_bf16": 8, "split_fp8": 14, "split_int8": 9, "split_int8_crt": 0}
+        start_s = {"split_bf16": 7, "split_fp8": 13, "split_int8": 7, "split_int8_crt": 0}
         for prec in [x for x in args.split.split(",") if x]:
             tried = []
             S = start_s[prec]
@@ -381,14 +382,17 @@ def main():
                 if d is None or d <= 5e-13 or S >= max_s[prec]:
                     break
                 S += 1
-            sg = [x for x in srecs if x["kernel"] == "slice_gemm"]
+            sg = [x for x in srecs if x["kernel"] in ("slice_gemm", "crt_gemm")]
             sg_ms = sum(x["ms"] for x in sg)
+            if prec == "split_int8_crt" and sg:
+                S = sg[0]["config"]  # moduli the library chose
             split[prec] = {"slices": S, "ms": round(sms, 2),
                            "eff_tflops": round(flop_eff / (sms * 1e-3) / 1e12, 3),
                            "speed_vs_fp64": round(ms / sms, 3), "rel_err_sampled_vs_oracle": None,
                            "slice_gemm_lowprec_tflops": round(sum(x["flops"] for x in sg) / (sg_ms * 1e-3) / 1e12, 1)
                            if sg_ms > 0 else None,
                            "split_kernels_ms": round(sum(x["ms"] for x in srecs if x["kernel"] == "split"), 2),
+                           "crt_combine_ms": round(sum(x["ms"] for x in srecs if x["kernel"] == "crt_combine"), 2),
                            "tried": tried}
             if r > 0:
                 samples[prec] = cs

@@ -271,30 +271,37 @@ int split_count(const Prec& pr, int64_t k) {
   return (pr.et == 3 && pr.S == 0) ? crt_default_moduli(k) : pr.S;
 }
 
-// Largest padded k of the CRT GEMM: k * 127^2 < 2^31 keeps int32 sums exact.
+// Largest padded k of the CRT GEMM (k is padded to 128): kp 127^2 < 2^31
+// keeps the int32 sums exact.
 constexpr int64_t kCrtMaxK = 133120;
 
 // Digit buffers of one split real product (reused by every real product).
-// The CRT form adds the residue planes of the product, N x m x n bytes.
+// Row length of the CRT form's residue planes (16-byte rows).
+int64_t crt_ldr(int64_t n) { return round_up(n, 16); }
+
+// The CRT form keeps the exponents and residue planes (N x m x crt_ldr(n)
+// bytes) of up to kCrtProducts real products, the real products of one
+// complex product, which one reconstruction pass then combines.
 struct SplitLayout {
   int64_t rows_pad, cols_pad, kp;
-  int S;
-  size_t a_bytes, b_bytes, ea_bytes, eb_bytes, r_bytes;
-  size_t total() const { return a_bytes + b_bytes + ea_bytes + eb_bytes + r_bytes; }
+  int S, sets;
+  size_t a_bytes, b_bytes, ea_bytes, eb_bytes, r_bytes;  // ea, eb, r: per set
+  size_t total() const { return a_bytes + b_bytes + size_t(sets) * (ea_bytes + eb_bytes + r_bytes); }
 };
 
 SplitLayout split_layout(const Prec& pr, int64_t m, int64_t n, int64_t k) {
   SplitLayout L{};
   const int es = pr.et == 0 ? 2 : 1;
   L.S = split_count(pr, k);
-  L.rows_pad = round_up(m, 128);
-  L.cols_pad = round_up(n, pr.et == 3 ? 128 : 64);
-  L.kp = round_up(k, 64);
+  L.sets = pr.et == 3 ? bq::kCrtProducts : 1;
+  L.rows_pad = round_up(m, pr.et == 3 ? 256 : 128);
+  L.cols_pad = round_up(n, pr.et == 3 ? 256 : 64);
+  L.kp = round_up(k, pr.et == 3 ? 128 : 64);
   L.a_bytes = align256(size_t(L.S) * size_t(L.rows_pad) * size_t(L.kp) * es);
   L.b_bytes = align256(size_t(L.S) * size_t(L.cols_pad) * size_t(L.kp) * es);
   L.ea_bytes = align256(size_t(L.rows_pad) * 4);
   L.eb_bytes = align256(size_t(L.cols_pad) * 4);
-  L.r_bytes = pr.et == 3 ? align256(size_t(L.S) * size_t(m) * size_t(n)) : 0;
+  L.r_bytes = pr.et == 3 ? align256(size_t(L.S) * size_t(m) * size_t(crt_ldr(n))) : 0;
   return L;
 }
 
@@ -407,7 +414,7 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
   if (k != kb) return fail(BQ_ERR_INVALID_VALUE, "inner dimensions of op(A) and op(B) differ");
   if (C->rows != m || C->cols != n) return fail(BQ_ERR_INVALID_VALUE, "C must be rows(op(A)) x cols(op(B))");
   if (pr.et == 3 && k > 0) {
-    if (round_up(k, 64) > kCrtMaxK)
+    if (round_up(k, 128) > kCrtMaxK)
       return fail(BQ_ERR_UNSUPPORTED, "CRT form: k above " + std::to_string(kCrtMaxK) + " is not supported");
     if (crt_bits(split_count(pr, k), k) < 1)
       return fail(BQ_ERR_INVALID_VALUE, "CRT form: too few moduli for this inner dimension");
@@ -561,14 +568,20 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   void* dig_b = nullptr;
   int* exp_a = nullptr;
   int* exp_b = nullptr;
-  signed char* res_planes = nullptr;
+  int* crt_ea[bq::kCrtProducts] = {};
+  int* crt_eb[bq::kCrtProducts] = {};
+  signed char* crt_res[bq::kCrtProducts] = {};
   if (pr.et >= 0 && k > 0) {
     sl = split_layout(pr, m, n, k);
     dig_a = wp; wp += sl.a_bytes;
     dig_b = wp; wp += sl.b_bytes;
-    exp_a = reinterpret_cast<int*>(wp); wp += sl.ea_bytes;
-    exp_b = reinterpret_cast<int*>(wp); wp += sl.eb_bytes;
-    res_planes = reinterpret_cast<signed char*>(wp); wp += sl.r_bytes;
+    for (int q = 0; q < sl.sets; ++q) {
+      crt_ea[q] = reinterpret_cast<int*>(wp); wp += sl.ea_bytes;
+      crt_eb[q] = reinterpret_cast<int*>(wp); wp += sl.eb_bytes;
+      crt_res[q] = reinterpret_cast<signed char*>(wp); wp += sl.r_bytes;
+    }
+    exp_a = crt_ea[0];
+    exp_b = crt_eb[0];
   }
   const bool crt = pr.et == 3;
   const int es = pr.et == 0 ? 2 : 1;
@@ -591,8 +604,8 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       ++sg.ntgt;
     }
     if (sg.ntgt == 0) return hipSuccess;
-    const int variant = crt ? 0 : bq::resolve_slice_variant(pr.et, S, slice_variant());
-    const int tiled = crt ? 1 : bq::slice_variant_tiled(variant);
+    const int variant = bq::resolve_slice_variant(pr.et, S, slice_variant());
+    const int tiled = bq::slice_variant_tiled(variant);
     // The left factor takes one exponent per row of op(A): along the stored
     // rows (row kernels) for N and C, along the stored columns (column
     // kernels, which also transpose the digits) for T and H; the right factor
@@ -609,52 +622,16 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
                 elems_x * 8.0 * (x2 ? 2 : 1) * 2.0 + double(sl.rows_pad) * double(sl.kp) * S * es);
-      hipError_t e = crt ? bq::launch_crt_split(S, xa, exp_a, dig_a, s)
-                         : bq::launch_split(pr.et, S, xa, exp_a, dig_a, s);
+      hipError_t e = bq::launch_split(pr.et, S, xa, exp_a, dig_a, s);
       tr.done();
       if (e != hipSuccess) return e;
     }
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, k, n, 0, 0.0,
                 elems_y * 8.0 * (y2 ? 2 : 1) * 2.0 + double(sl.cols_pad) * double(sl.kp) * S * es);
-      hipError_t e = crt ? bq::launch_crt_split(S, ya, exp_b, dig_b, s)
-                         : bq::launch_split(pr.et, S, ya, exp_b, dig_b, s);
+      hipError_t e = bq::launch_split(pr.et, S, ya, exp_b, dig_b, s);
       tr.done();
       if (e != hipSuccess) return e;
-    }
-    if (crt) {
-      // One exact INT8 GEMM per modulus into residue planes, then the
-      // Chinese remainder reconstruction and the targets.
-      const bq::CrtGemmArgs cg{dig_a, dig_b, sl.rows_pad * sl.kp, sl.cols_pad * sl.kp, sl.kp, m, n,
-                               res_planes, m * n, n};
-      {
-        Tracer tr(h, s, BQ_KERNEL_CRT_GEMM, S, m, n, k, double(S) * 2.0 * double(m) * double(n) * double(k), 0.0);
-        hipError_t e = bq::launch_crt_gemm(S, cg, s);
-        tr.done();
-        if (e != hipSuccess) return e;
-      }
-      bq::CrtCombineArgs cc{};
-      cc.res = res_planes;
-      cc.plane_r = m * n;
-      cc.ldr = n;
-      cc.ea = exp_a;
-      cc.eb = exp_b;
-      cc.m = m;
-      cc.n = n;
-      cc.bits = beta;
-      cc.ntgt = sg.ntgt;
-      int rw = 0;
-      for (int q = 0; q < sg.ntgt; ++q) {
-        cc.c[q] = sg.c[q];
-        cc.coef[q] = sg.coef[q];
-        cc.mode[q] = sg.mode[q];
-        rw += sg.mode[q] == bq::TGT_ACCUM ? 2 : 1;
-      }
-      cc.ldc = C->ld;
-      Tracer tr(h, s, BQ_KERNEL_CRT_COMBINE, S, m, n, 0, 0.0, double(m) * double(n) * (double(S) + 8.0 * rw));
-      hipError_t e = bq::launch_crt_combine(S, cc, s);
-      tr.done();
-      return e;
     }
     sg.a = dig_a;
     sg.b = dig_b;
@@ -671,6 +648,41 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     const double pairs = double(S) * double(S + 1) / 2.0;
     Tracer tr(h, s, BQ_KERNEL_SLICE_GEMM, S, m, n, k, pairs * 2.0 * double(m) * double(n) * double(k), 0.0);
     hipError_t e = bq::launch_slice_gemm(pr.et, S, variant, sg, s);
+    tr.done();
+    return e;
+  };
+
+  // CRT form: one real product T = X Y into residue set q (exponents and
+  // residue planes of its INT8 GEMMs); crt_combine reconstructs it.
+  const int64_t ldr = crt_ldr(n);
+  auto crt_product = [&](const double* x1, const double* x2, double xw2, int64_t ldx, const double* y1,
+                         const double* y2, double yw2, int64_t ldy, int q) -> hipError_t {
+    bq::SplitArgs xa = pl.ta ? bq::SplitArgs{x1, x2, 1.0, xw2, ldx, k, m, 0, sl.rows_pad, sl.kp,
+                                             sl.rows_pad * sl.kp, beta, 0, 0, 1}
+                             : bq::SplitArgs{x1, x2, 1.0, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp,
+                                             sl.rows_pad * sl.kp, beta, 0, 1, 1};
+    bq::SplitArgs ya = pl.tb ? bq::SplitArgs{y1, y2, 1.0, yw2, ldy, n, k, sl.cols_pad, 0, sl.kp,
+                                             sl.cols_pad * sl.kp, beta, 0, 1, 1}
+                             : bq::SplitArgs{y1, y2, 1.0, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp,
+                                             sl.cols_pad * sl.kp, beta, 0, 0, 1};
+    {
+      Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
+                double(m) * double(k) * 8.0 * (x2 ? 2 : 1) * 2.0 + double(sl.rows_pad) * double(sl.kp) * S);
+      hipError_t e = bq::launch_crt_split(S, xa, crt_ea[q], dig_a, s);
+      tr.done();
+      if (e != hipSuccess) return e;
+    }
+    {
+      Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, k, n, 0, 0.0,
+                double(k) * double(n) * 8.0 * (y2 ? 2 : 1) * 2.0 + double(sl.cols_pad) * double(sl.kp) * S);
+      hipError_t e = bq::launch_crt_split(S, ya, crt_eb[q], dig_b, s);
+      tr.done();
+      if (e != hipSuccess) return e;
+    }
+    const bq::CrtGemmArgs cg{dig_a, dig_b, sl.rows_pad * sl.kp, sl.cols_pad * sl.kp, sl.kp, m, n,
+                             crt_res[q], m * ldr, ldr};
+    Tracer tr(h, s, BQ_KERNEL_CRT_GEMM, S, m, n, k, double(S) * 2.0 * double(m) * double(n) * double(k), 0.0);
+    hipError_t e = bq::launch_crt_gemm(S, cg, s);
     tr.done();
     return e;
   };
@@ -758,6 +770,63 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
         rps.push_back({L.i, nullptr, 0.0, R.r, nullptr, 0.0, 0.0, L.s});
       } else {
         rps.push_back({L.r, nullptr, 0.0, R.r, nullptr, 0.0, 1.0, 0.0});
+      }
+      if (crt) {
+        // The real products of this complex product into residue sets, then
+        // one reconstruction pass: target q takes sum_p coef[q][p] T_p.
+        bq::CrtCombineArgs cc{};
+        int slot_of[8];
+        for (int w = 0; w < 8; ++w) slot_of[w] = -1;
+        std::vector<int> used;
+        for (size_t pi = 0; pi < rps.size(); ++pi) {
+          const RealProd& rp = rps[pi];
+          const int col = (int)used.size();
+          bool any = false;
+          for (const Tgt& t : p.tgts) {
+            const Cplx c = cmul(t.coef, rot);
+            const int ws[2] = {t.w, t.w + 4};
+            const double vs[2] = {c.re * rp.aR - c.im * rp.aI, c.re * rp.aI + c.im * rp.aR};
+            for (int u = 0; u < 2; ++u) {
+              if (!(out_mask >> ws[u] & 1) || vs[u] == 0.0) continue;
+              if (slot_of[ws[u]] < 0) {
+                slot_of[ws[u]] = cc.ntgt;
+                cc.c[cc.ntgt++] = C->comp[ws[u]];
+              }
+              cc.coef[slot_of[ws[u]]][col] += vs[u];
+              any = true;
+            }
+          }
+          if (any) used.push_back((int)pi);
+        }
+        if (cc.ntgt == 0) continue;
+        for (size_t q = 0; q < used.size(); ++q) {
+          const RealProd& rp = rps[used[q]];
+          hipError_t e = crt_product(rp.x1, rp.x2, rp.xw2, L.ld, rp.y1, rp.y2, rp.yw2, R.ld, (int)q);
+          if (e != hipSuccess) return hip_fail(e, "split-precision launch");
+          cc.res[q] = crt_res[q];
+          cc.ea[q] = crt_ea[q];
+          cc.eb[q] = crt_eb[q];
+        }
+        cc.np = (int)used.size();
+        for (int w = 0; w < 8; ++w) {
+          if (slot_of[w] < 0) continue;
+          cc.mode[slot_of[w]] = touched[w] ? bq::TGT_ACCUM : bq::TGT_WRITE;
+          touched[w] = true;
+        }
+        cc.plane_r = m * ldr;
+        cc.ldr = ldr;
+        cc.m = m;
+        cc.n = n;
+        cc.bits = beta;
+        cc.ldc = C->ld;
+        int rw = 0;
+        for (int q = 0; q < cc.ntgt; ++q) rw += cc.mode[q] == bq::TGT_ACCUM ? 2 : 1;
+        Tracer tr(h, s, BQ_KERNEL_CRT_COMBINE, S, m, n, 0, 0.0,
+                  double(m) * double(n) * (double(S) * cc.np + 8.0 * rw));
+        hipError_t e = bq::launch_crt_combine(S, cc, s);
+        tr.done();
+        if (e != hipSuccess) return hip_fail(e, "split-precision launch");
+        continue;
       }
       for (const RealProd& rp : rps) {
         std::vector<std::pair<int, double>> outs;

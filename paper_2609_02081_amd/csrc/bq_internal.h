@@ -113,33 +113,38 @@ struct GroupedItem {
   int tm, tn;
 };
 
-// CRT-based split form (bq_split.hip): residue planes and their GEMMs.
+// CRT-based split form (bq_crt.hip): residue planes and their GEMMs.
 constexpr int kMaxCrtModuli = 20;
 struct CrtGemmArgs {
-  const void* a;  // residues of X: [N][rows_pad (128)][kp], tiled 64-byte layout
-  const void* b;  // residues of Y: [N][cols_pad (128)][kp], same
+  const void* a;  // residues of X: [N][rows_pad (256)][kp], tiled 64-byte layout
+  const void* b;  // residues of Y: [N][cols_pad (256)][kp], same
   int64_t plane_a, plane_b;  // bytes between modulus planes
   int64_t kp;
   int64_t m, n;
-  signed char* out;  // result residues [N][m][ldr]
+  signed char* out;  // result residues [N][m][ldr], ldr a multiple of 16
   int64_t plane_r, ldr;
 };
+// Up to kCrtProducts real products T_p of one complex product (the Gauss
+// form has three), each from its own residue planes and exponents; target q
+// gets sum_p coef[q][p] T_p, written or added once.
+constexpr int kCrtProducts = 3;
 struct CrtCombineArgs {
-  const signed char* res;
+  int np;
+  const signed char* res[kCrtProducts];
+  const int* ea[kCrtProducts];
+  const int* eb[kCrtProducts];
   int64_t plane_r, ldr;
-  const int* ea;
-  const int* eb;
   int64_t m, n;
   int bits;
   int ntgt;
   double* c[kMaxSliceTargets];
-  double coef[kMaxSliceTargets];
+  double coef[kMaxSliceTargets][kCrtProducts];
   int mode[kMaxSliceTargets];
   int64_t ldc;
   // Filled by the launcher: Chinese remainder constants of the N moduli.
-  uint32_t cl[kMaxCrtModuli][4];  // c_i modulo 2^128, 32-bit limbs, low first
-  double frac[kMaxCrtModuli];     // c_i / M
-  uint32_t ml[4];                 // M modulo 2^128
+  double cpart[kMaxCrtModuli][4];  // c_i modulo 2^128 as four 32-bit parts, low first
+  double frac[kMaxCrtModuli];      // c_i / M
+  double mpart[4];                 // M modulo 2^128, the same way
 };
 
 // Complex linear map of the 8 components into an R x R complex buffer
@@ -187,6 +192,8 @@ hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_pr
 // Split-precision kernels (bq_split.hip).  et: 0 = BF16 digits (beta 7),
 // 1 = OCP FP8 E4M3 digits (beta 4), 2 = INT8 digits (beta 7, headroom 1).
 hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t s);
+// Row (a.left) or column exponents of a split operand into exps.
+hipError_t launch_split_exponents(const SplitArgs& a, int* exps, hipStream_t s);
 hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t s);  // variant -1: default
 int resolve_slice_variant(int et, int S, int variant);  // the shape launch_slice_gemm runs
 int slice_variant_tiled(int variant);                    // digit layout the shape reads (SplitArgs::tiled)

@@ -23,28 +23,9 @@
 #include <cmath>
 #include <vector>
 
-#include "bq_internal.h"
+#include "bq_split_common.h"
 
 namespace bq {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef double d4s __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef int i4v __attribute__((ext_vector_type(4)));
-typedef int i2v __attribute__((ext_vector_type(2)));
-
-// Value of the split operand: w1 * s1 + w2 * s2 (s2 may be absent).  The
-// FP64 path forms its Gauss sums with the same single rounding.
-__device__ __forceinline__ double operand_value(const SplitArgs& a, int64_t off) {
-  const double x = a.s1[off];
-  return a.s2 ? __builtin_fma(a.w2, a.s2[off], a.w1 * x) : a.w1 * x;
-}
-
-__device__ __forceinline__ int exp_of(double x) {
-  int e;
-  (void)frexp(x, &e);
-  return x == 0.0 ? INT_MIN : e;
-}
 
 // Exponents: e[r] = max over the reduced dimension of frexp exponents
 // (rows of the left operand, columns of the right one).  exps must hold
@@ -58,7 +39,7 @@ __global__ void __launch_bounds__(256) split_exp_left(const SplitArgs a, int* ex
     const int64_t c = c0 + j;
     if (c < a.cols) e = max(e, exp_of(operand_value(a, r * a.ld + c)));
   }
-  if (e != INT_MIN) e += a.head;
+  if (!exp_special(e)) e += a.head;
   for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
   __shared__ int red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
@@ -83,7 +64,7 @@ __global__ void __launch_bounds__(256) split_exp_right(const SplitArgs a, int* e
   __syncthreads();
   if (threadIdx.x < 64) {
     e = max(max(red[threadIdx.x], red[threadIdx.x + 64]), max(red[threadIdx.x + 128], red[threadIdx.x + 192]));
-    if (c < a.cols && e != INT_MIN) atomicMax(&exps[c], e + a.head);
+    if (c < a.cols && e != INT_MIN) atomicMax(&exps[c], exp_special(e) ? e : e + a.head);
   }
 }
 
@@ -92,50 +73,10 @@ __global__ void __launch_bounds__(256) fill_int(int* p, int64_t n, int v) {
   if (i < n) p[i] = v;
 }
 
-// Chunk position of logical chunk ch in tile row r (rows of 4 chunks).
-// 16-byte chunks (rows of 64 bytes): a 16-byte LDS access is served 8 lanes
-// at a time over 32 banks (128 bytes); a fragment read has 8 lanes on 8
-// consecutive rows at one logical chunk, and rows 2j, 2j + 1 share a
-// 128-byte bank line offset by 64 bytes, so even rows must take 4 distinct
-// positions, and odd rows too: position = ch ^ f(r) with f built from row
-// bits 1..3.  8-byte chunks (rows of 32 bytes): 16 lanes per access on 16
-// consecutive rows; rows r and r + 4 share banks, so f = bits 2..3.
-template <int CH>
-__device__ __forceinline__ int swz_chunk(int r, int ch) {
-  if constexpr (CH == 16) return ch ^ ((((r >> 1) ^ (r >> 3)) & 1) | ((r >> 1) & 2));
-  else return ch ^ ((r >> 2) & 3);
-}
-
-// Tiled digit layouts (direct-to-LDS slice GEMMs): within one slice, the 64
-// rows x one k-step (RB = 64 or 32 bytes per row) of row tile rt, k-step kt
-// form one 64 RB-byte block at (rt * nk + kt) * 64 RB, stored in the LDS
-// order (row r at r * RB, logical 16-byte chunk ch at the swizzled position),
-// so that a straight copy lands the tile ready for fragment reads.
-// Rows of 32 bytes (two chunks): a 16-byte fragment read has 8 lanes on 8
-// consecutive rows at one chunk, rows r and r + 4 share banks, so the chunk
-// position flips with row bit 2.
-__device__ __forceinline__ int swz_chunk32(int r, int ch) { return ch ^ ((r >> 2) & 1); }
-
-template <int RB>
-__device__ __forceinline__ int64_t slice_tile_offset(int64_t r, int64_t byte_in_row, int64_t row_bytes) {
-  const int64_t nk = row_bytes / RB, kt = byte_in_row / RB;
-  const int rr = (int)(r & 63), b = (int)(byte_in_row % RB);
-  const int pos = RB == 64 ? swz_chunk<16>(rr, b >> 4) : swz_chunk32(rr, b >> 4);
-  return ((r >> 6) * nk + kt) * (64 * RB) + rr * RB + pos * 16 + (b & 15);
-}
-
-// Byte offset of the digit at (row r, byte b of the row) in one slice, for
-// layout `tiled` (0: row-major with rows of row_bytes).
-__device__ __forceinline__ int64_t digit_offset(int tiled, int64_t r, int64_t b, int64_t row_bytes) {
-  if (tiled == 1) return slice_tile_offset<64>(r, b, row_bytes);
-  if (tiled == 2) return slice_tile_offset<32>(r, b, row_bytes);
-  return r * row_bytes + b;
-}
-
 // Digits of one element: q[0..S-1] from x and its row/column exponent.
 template <int S>
 __device__ __forceinline__ void digits(double x, int e, int beta, float* q) {
-  double y = (e == INT_MIN) ? 0.0 : ldexp(x, -e);
+  double y = exp_special(e) ? 0.0 : ldexp(x, -e);
 #pragma unroll
   for (int s = 1; s <= S; ++s) {
     const double d = rint(ldexp(y, beta * s));
@@ -304,7 +245,7 @@ __device__ __forceinline__ void store_tile(const SliceGemmArgs& g, const d4s (&a
         const int64_t c = c0 + j * 16 + fr;
         if (r >= g.m || c >= g.n) continue;
         const int ea = g.ea[r], eb = g.eb[c];
-        const double t = (ea == INT_MIN || eb == INT_MIN) ? 0.0 : ldexp(acc[i][j][v], ea + eb);
+        const double t = exp_scaled(acc[i][j][v], ea, eb, 0);
         const int64_t off = r * g.ldc + c;
         for (int q = 0; q < g.ntgt; ++q) {
           double val = g.coef[q] * t;
@@ -315,19 +256,6 @@ __device__ __forceinline__ void store_tile(const SliceGemmArgs& g, const d4s (&a
 }
 
 
-
-// Block -> output tile, XCD-aware and grouped by 8 tile rows (as in the
-// FP64 GEMM): consecutive block ids land on different XCDs, so each XCD
-// gets a contiguous run of tiles.
-__device__ __forceinline__ void slice_tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int T = tiles_m * tiles_n, w = blockIdx.x;
-  const int x = w % 8, slot = w / 8, base = T / 8, rem = T % 8;
-  const int t = x * base + (x < rem ? x : rem) + slot;
-  const int per_group = 8 * tiles_n, group = t / per_group, first_m = group * 8;
-  const int gm = min(tiles_m - first_m, 8), in_g = t - group * per_group;
-  tm = first_m + in_g % gm;
-  tn = in_g / gm;
-}
 
 template <int ET, int S, int WM, int MI, int CACHE_B, int NSTAGE, int WPE, int PERSIST>
 __global__ void __launch_bounds__(WM * 2 * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
@@ -584,8 +512,6 @@ slice_gemm(const SliceGemmArgs g) {
 // Level sums stay in registers across k-steps and go to FP64 every
 // g.kflush k-steps.
 // ---------------------------------------------------------------------------
-typedef __attribute__((address_space(3))) void* lds_void_ptr;
-
 template <int ET, int S>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 slice_gemm_dma(const SliceGemmArgs g) {
@@ -724,28 +650,6 @@ slice_gemm_dma(const SliceGemmArgs g) {
 typedef int i16v __attribute__((ext_vector_type(16)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
-// Workgroup barrier without the memory fence of __syncthreads (which would
-// wait for every load in flight, prefetches included): the kernels order
-// their LDS traffic themselves (wait_vm before, fragment reads consumed
-// before the barrier).
-__device__ __forceinline__ void block_sync() {
-  __builtin_amdgcn_sched_barrier(0);
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-// s_waitcnt vmcnt(N): wait until at most N vector-memory loads are pending.
-#define BQ_WAIT_VM_CASE(K) \
-  else if constexpr (N == K) asm volatile("s_waitcnt vmcnt(" #K ")" ::: "memory");
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N <= 15, "vmcnt range used here");
-  if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  BQ_WAIT_VM_CASE(1) BQ_WAIT_VM_CASE(2) BQ_WAIT_VM_CASE(3) BQ_WAIT_VM_CASE(4) BQ_WAIT_VM_CASE(5)
-  BQ_WAIT_VM_CASE(6) BQ_WAIT_VM_CASE(7) BQ_WAIT_VM_CASE(8) BQ_WAIT_VM_CASE(9) BQ_WAIT_VM_CASE(10)
-  BQ_WAIT_VM_CASE(11) BQ_WAIT_VM_CASE(12) BQ_WAIT_VM_CASE(13) BQ_WAIT_VM_CASE(14) BQ_WAIT_VM_CASE(15)
-}
-#undef BQ_WAIT_VM_CASE
 
 template <int ET>
 struct SliceTraits32;
@@ -778,7 +682,7 @@ __device__ __forceinline__ void store_tile32(const SliceGemmArgs& g, const doubl
     const int64_t c = c0 + (lane & 31);
     if (r >= g.m || c >= g.n) continue;
     const int ea = g.ea[r], eb = g.eb[c];
-    const double t = (ea == INT_MIN || eb == INT_MIN) ? 0.0 : ldexp(acc[v], ea + eb);
+    const double t = exp_scaled(acc[v], ea, eb, 0);
     const int64_t off = r * g.ldc + c;
     for (int q = 0; q < g.ntgt; ++q) {
       double val = g.coef[q] * t;
@@ -922,287 +826,30 @@ slice_gemm_x32(const SliceGemmArgs g) {
   store_tile32(g, acc, m0 + wm0, n0 + wn0, lane);
 }
 
-// ===========================================================================
-// CRT-based split form (Ozaki scheme II, integer-modular).
-//
-// A real product T = X Y: every row of X (column of Y) gets its frexp
-// exponent e (f), the scaled integers X' = rint(x 2^(b - e)) (|X'| <= 2^b,
-// b <= 53, exact in FP64) are written as symmetric residues modulo N odd,
-// pairwise coprime moduli p_i <= 255 (one signed byte each), every modulus
-// is one exact INT8 GEMM with int32 sums (|sum| <= k 127^2 < 2^31), its
-// result reduced to a residue again, and P = X'Y' is recovered from its
-// residues r_i by the Chinese remainder theorem: P = sum_i r_i c_i - q M
-// with M = p_1 ... p_N, c_i = (M / p_i) ((M / p_i)^-1 mod p_i) and q the
-// integer nearest to sum_i r_i (c_i / M).  The bound |P| <= k 2^(2b) <
-// 2^127 lets that sum run in 128-bit wraparound integers, so P is exact;
-// it is rounded to FP64 once and T = P 2^(e + f - 2b) is the correctly
-// rounded product of the scaled integers.  N moduli with M > 2 k 2^(2b)
-// carry b bits.
-// ===========================================================================
-constexpr int kCrtModuli[kMaxCrtModuli] = {255, 253, 251, 247, 241, 239, 233, 229, 227, 223,
-                                           211, 199, 197, 193, 191, 181, 179, 173, 167, 163};
-
-struct CrtTables {
-  int lo26[kMaxCrtModuli];  // 2^26 mod p_i
-};
-constexpr CrtTables make_crt_tables() {
-  CrtTables t{};
-  for (int i = 0; i < kMaxCrtModuli; ++i) t.lo26[i] = (1 << 26) % kCrtModuli[i];
-  return t;
-}
-__constant__ CrtTables kCrt = make_crt_tables();
-
-// Symmetric residue of t (|t| < 2^31) modulo an odd p: [-(p-1)/2, (p-1)/2].
-__device__ __forceinline__ int sym_mod(int t, int p) {
-  t %= p;
-  const int h = (p - 1) >> 1;
-  return t > h ? t - p : (t < -h ? t + p : t);
-}
-
-// Residues of one element: X' = rint(x 2^(b - e)) split as hi 2^26 + lo
-// (|hi| <= 2^27, 0 <= lo < 2^26) so every step is 32-bit.
-template <int N>
-__device__ __forceinline__ void crt_residues(double x, int e, int b, signed char* r) {
-  const double y = (e == INT_MIN) ? 0.0 : rint(ldexp(x, b - e));
-  const int64_t xi = (int64_t)y;
-  const int hi = (int)(xi >> 26);
-  const int lo = (int)(xi & ((1 << 26) - 1));
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const int p = kCrtModuli[i];
-    r[i] = (signed char)sym_mod((hi % p) * kCrt.lo26[i] + lo % p, p);
-  }
-}
-
-// Left factor: residue planes R[i][row][kk] in the tiled 64-byte layout.
-// Thread: 8 consecutive kk of one row.  grid.x = rows_pad, grid.y = kp / 2048.
-template <int N>
-__global__ void __launch_bounds__(256) crt_split_left(const SplitArgs a, const int* exps, void* out) {
-  const int64_t r = blockIdx.x;
-  const int64_t kk0 = (int64_t)blockIdx.y * 2048 + threadIdx.x * 8;
-  if (kk0 >= a.kp) return;
-  const int e = (r < a.rows) ? exps[r] : INT_MIN;
-  signed char q[8][N];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int64_t c = kk0 + t;
-    const double x = (r < a.rows && c < a.cols) ? operand_value(a, r * a.ld + c) : 0.0;
-    crt_residues<N>(x, e, a.beta, q[t]);
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const int64_t o = (int64_t)i * a.slice_stride + digit_offset(1, r, kk0, a.kp);
-    i2v v;
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-      v[t] = (int)(unsigned char)q[4 * t][i] | ((int)(unsigned char)q[4 * t + 1][i] << 8) |
-             ((int)(unsigned char)q[4 * t + 2][i] << 16) | ((int)(unsigned char)q[4 * t + 3][i] << 24);
-    *reinterpret_cast<i2v*>(static_cast<unsigned char*>(out) + o) = v;
-  }
-}
-
-// Right factor (k x n): residues stored transposed, R[i][col][kk], through
-// an LDS tile of 64 (kk) x 64 (col).  grid.x = cols_pad / 64, grid.y = kp / 64.
-template <int N>
-__global__ void __launch_bounds__(256) crt_split_right(const SplitArgs a, const int* exps, void* out) {
-  __shared__ __attribute__((aligned(16))) unsigned char tile[N][64][64 + 16];
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  const int64_t k0 = (int64_t)blockIdx.y * 64;
-  const int tc = threadIdx.x & 63;
-  const int64_t c = c0 + tc;
-  const int e = (c < a.cols) ? exps[c] : INT_MIN;
-  for (int rr = threadIdx.x >> 6; rr < 64; rr += 4) {
-    const int64_t kk = k0 + rr;
-    const double x = (c < a.cols && kk < a.rows) ? operand_value(a, kk * a.ld + c) : 0.0;
-    signed char q[N];
-    crt_residues<N>(x, e, a.beta, q);
-#pragma unroll
-    for (int i = 0; i < N; ++i) tile[i][tc][rr] = (unsigned char)q[i];
-  }
-  __syncthreads();
-  for (int w = threadIdx.x; w < N * 64 * 4; w += 256) {
-    const int i = w / 256;
-    const int rem = w % 256;
-    const int cc = rem / 4, p = rem % 4;
-    const i4v v = *reinterpret_cast<const i4v*>(&tile[i][cc][p * 16]);
-    const int64_t o = digit_offset(1, c0 + cc, k0 + p * 16, a.kp);
-    *reinterpret_cast<i4v*>(static_cast<unsigned char*>(out) + (int64_t)i * a.slice_stride + o) = v;
-  }
-}
-
-// One INT8 GEMM per modulus (blockIdx.y): residue planes of X (rows padded
-// to 128) and Y (columns padded to 128) in the tiled 64-byte layout, a 128 x
-// 128 block of 4 waves (64 x 64 each, 16 v_mfma_i32_16x16x64_i8 per k-step),
-// four LDS stages filled straight from global memory three k-steps ahead,
-// every wave moving 4 of the stage's 16 KB.  The int32 result is reduced to
-// its symmetric residue and stored as a byte plane R[i][row][col].
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-crt_gemm(const CrtGemmArgs g) {
-  constexpr int BM = 128, BN = 128, ROWB = 64, TILE = 64 * ROWB;  // 4 KB per 64-row tile
-  constexpr int STAGE = 4 * TILE;                                  // two A tiles, two B tiles
-  constexpr int NST = 4, NPW = 4;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[NST * STAGE];
-  const int mod = blockIdx.y;
-  const int p = kCrtModuli[mod];
-
-  const int tiles_m = (int)((g.m + BM - 1) / BM);
-  const int tiles_n = (int)((g.n + BN - 1) / BN);
-  int tm, tn;
-  slice_tile_coords(tiles_m, tiles_n, tm, tn);
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-  const int fr = lane & 15, fg = lane >> 4;
-
-  const int64_t nk = g.kp / ROWB;
-  const int64_t run = nk * TILE;
-  const unsigned char* ga = static_cast<const unsigned char*>(g.a) + mod * g.plane_a + (int64_t)(2 * tm) * run;
-  const unsigned char* gb = static_cast<const unsigned char*>(g.b) + mod * g.plane_b + (int64_t)(2 * tn) * run;
-  const int nrec = (int)(uint32_t)(2 * run);
-  // 1 KB piece q of a stage: q < 8 A (tile q / 4, quarter q % 4), else B.
-  auto dma = [&](int q, int64_t kt, int st) {
-    const int side = q >> 3, t = (q >> 2) & 1, quarter = q & 3;
-    const __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc((void*)(side ? gb : ga), (short)0, nrec, 0x00020000);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_ptr)(lds + st * STAGE + q * 1024), 16,
-                                             (int)(t * run) + quarter * 1024 + lane * 16, (int)(kt * TILE), 0, 0);
-  };
-  auto frag = [&](const unsigned char* base, int row) {
-    return *reinterpret_cast<const i4v*>(base + row * ROWB + swz_chunk<16>(row & 63, fg) * 16);
-  };
-
-  i4v acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = i4v{0, 0, 0, 0};
-
-  // Prologue: k-steps 0..NST-2 (past the end: the last one again).
-#pragma unroll
-  for (int s = 0; s < NST - 1; ++s)
-#pragma unroll
-    for (int i = 0; i < NPW; ++i) dma(wave * NPW + i, s < nk ? s : nk - 1, s);
-  wait_vm<(NST - 2) * NPW>();
-  block_sync();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int st = (int)(kt % NST);
-    const int sn = (int)((kt + NST - 1) % NST);
-    const int64_t knext = kt + NST - 1 < nk ? kt + NST - 1 : nk - 1;
-    const unsigned char* ta = lds + st * STAGE;
-    const unsigned char* tb = ta + 2 * TILE;
-    i4v fa[4], fb[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) fa[i] = frag(ta, wm0 + i * 16 + fr);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) fb[j] = frag(tb, wn0 + j * 16 + fr);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
-      dma(wave * NPW + i, knext, sn);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    // Stage kt + 1 is complete once at most the loads of the last two
-    // k-steps (kt + NST - 2, kt + NST - 1) are still out.
-    wait_vm<(NST - 2) * NPW>();
-    block_sync();
-  }
-  wait_vm<0>();
-
-  signed char* out = g.out + (int64_t)mod * g.plane_r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = m0 + wm0 + i * 16 + 4 * fg + v;
-        const int64_t c = n0 + wn0 + j * 16 + fr;
-        if (r < g.m && c < g.n) out[r * g.ldr + c] = (signed char)sym_mod(acc[i][j][v], p);
-      }
-}
-
-// |P| rounded to FP64 once (round to nearest even): the leading 64 bits
-// with every lower bit folded into a sticky bit, converted as two exact
-// 32-bit halves joined by one fma.
-__device__ __forceinline__ double u128_to_double(unsigned __int128 u) {
-  const uint64_t hi = (uint64_t)(u >> 64);
-  int sh = 0;
-  uint64_t top = (uint64_t)u;
-  if (hi != 0) {
-    sh = 64 - __builtin_clzll(hi);
-    const unsigned __int128 rest = u & ((((unsigned __int128)1) << sh) - 1);
-    top = (uint64_t)(u >> sh) | (uint64_t)(rest != 0);
-  }
-  const double d = __builtin_fma((double)(uint32_t)(top >> 32), 4294967296.0, (double)(uint32_t)top);
-  return ldexp(d, sh);
-}
-
-// P from its residues, T = P 2^(e + f - 2b), coef * T into every target.
-// One thread per element; grid.x = rows * ceil(cols / 256).  The 128-bit
-// sum is kept as four signed 64-bit column sums of 32-bit limbs
-// (|r c_limb| < 2^39), joined once at the end.
-template <int N>
-__global__ void __launch_bounds__(256) crt_combine(const CrtCombineArgs g) {
-  const int64_t bpr = (g.n + 255) / 256;
-  const int64_t r = blockIdx.x / bpr;
-  const int64_t c = (blockIdx.x % bpr) * 256 + threadIdx.x;
-  if (r >= g.m || c >= g.n) return;
-  int64_t acc[4] = {0, 0, 0, 0};
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const int v = g.res[(int64_t)i * g.plane_r + r * g.ldr + c];
-    s = __builtin_fma((double)v, g.frac[i], s);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] += (int64_t)v * (int64_t)g.cl[i][j];
-  }
-  const int64_t q = (int64_t)rint(s);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] -= q * (int64_t)g.ml[j];
-  unsigned __int128 P = (unsigned __int128)(__int128)acc[0];
-#pragma unroll
-  for (int j = 1; j < 4; ++j) P += ((unsigned __int128)(__int128)acc[j]) << (32 * j);
-  __int128 Ps = (__int128)P;
-  if (N <= 16) {
-    // M < 2^125: an estimate of q one off leaves P - M or P + M, both in range.
-    const __int128 M = (__int128)(((unsigned __int128)g.ml[3] << 96) | ((unsigned __int128)g.ml[2] << 64) |
-                                  ((unsigned __int128)g.ml[1] << 32) | (unsigned __int128)g.ml[0]);
-    const __int128 half = (M - 1) >> 1;
-    if (Ps > half) Ps -= M;
-    else if (Ps < -half) Ps += M;
-  }
-  const bool neg = Ps < 0;
-  const double a = u128_to_double((unsigned __int128)(neg ? -Ps : Ps));
-  const int ea = g.ea[r], eb = g.eb[c];
-  const double t = (ea == INT_MIN || eb == INT_MIN) ? 0.0 : ldexp(neg ? -a : a, ea + eb - 2 * g.bits);
-  const int64_t off = r * g.ldc + c;
-  for (int q2 = 0; q2 < g.ntgt; ++q2) {
-    double val = g.coef[q2] * t;
-    if (g.mode[q2] == TGT_ACCUM) val += g.c[q2][off];
-    g.c[q2][off] = val;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int ET, int S>
-static hipError_t launch_split_s(const SplitArgs& a, int* exps, void* out, hipStream_t st) {
+hipError_t launch_split_exponents(const SplitArgs& a, int* exps, hipStream_t st) {
   const int64_t nexp = a.left ? a.rows_pad : a.cols_pad;
   hipLaunchKernelGGL(fill_int, dim3((unsigned)((nexp + 255) / 256)), dim3(256), 0, st, exps, nexp, INT_MIN);
-  if (a.left) {
+  if (a.left)
     hipLaunchKernelGGL(split_exp_left, dim3((unsigned)a.rows, (unsigned)((a.cols + 2047) / 2048)), dim3(256), 0,
                        st, a, exps);
-    hipLaunchKernelGGL((split_digits_left<ET, S>), dim3((unsigned)a.rows_pad, (unsigned)((a.kp + 2047) / 2048)),
-                       dim3(256), 0, st, a, exps, out);
-  } else {
+  else
     hipLaunchKernelGGL(split_exp_right, dim3((unsigned)((a.cols + 63) / 64), (unsigned)((a.rows + 1023) / 1024)),
                        dim3(256), 0, st, a, exps);
+  return hipGetLastError();
+}
+
+template <int ET, int S>
+static hipError_t launch_split_s(const SplitArgs& a, int* exps, void* out, hipStream_t st) {
+  if (hipError_t e = launch_split_exponents(a, exps, st); e != hipSuccess) return e;
+  if (a.left)
+    hipLaunchKernelGGL((split_digits_left<ET, S>), dim3((unsigned)a.rows_pad, (unsigned)((a.kp + 2047) / 2048)),
+                       dim3(256), 0, st, a, exps, out);
+  else
     hipLaunchKernelGGL((split_digits_right<ET, S>), dim3((unsigned)(a.cols_pad / 64), (unsigned)(a.kp / 64)),
                        dim3(256), 0, st, a, exps, out);
-  }
   return hipGetLastError();
 }
 
@@ -1334,128 +981,6 @@ hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g,
 }
 
 
-// CRT-based split form launchers.
-template <int N>
-static hipError_t launch_crt_split_n(const SplitArgs& a, int* exps, void* out, hipStream_t st) {
-  const int64_t nexp = a.left ? a.rows_pad : a.cols_pad;
-  hipLaunchKernelGGL(fill_int, dim3((unsigned)((nexp + 255) / 256)), dim3(256), 0, st, exps, nexp, INT_MIN);
-  if (a.left) {
-    hipLaunchKernelGGL(split_exp_left, dim3((unsigned)a.rows, (unsigned)((a.cols + 2047) / 2048)), dim3(256), 0,
-                       st, a, exps);
-    hipLaunchKernelGGL((crt_split_left<N>), dim3((unsigned)a.rows_pad, (unsigned)((a.kp + 2047) / 2048)),
-                       dim3(256), 0, st, a, exps, out);
-  } else {
-    hipLaunchKernelGGL(split_exp_right, dim3((unsigned)((a.cols + 63) / 64), (unsigned)((a.rows + 1023) / 1024)),
-                       dim3(256), 0, st, a, exps);
-    hipLaunchKernelGGL((crt_split_right<N>), dim3((unsigned)(a.cols_pad / 64), (unsigned)(a.kp / 64)), dim3(256), 0,
-                       st, a, exps, out);
-  }
-  return hipGetLastError();
-}
-
-// Chinese remainder constants of the first N moduli, exact (base-2^32
-// limbs): c_i = M_i (M_i^-1 mod p_i) with M_i = M / p_i, kept modulo 2^128,
-// and c_i / M in FP64.
-struct CrtConsts {
-  uint32_t cl[kMaxCrtModuli][4];
-  double frac[kMaxCrtModuli];
-  uint32_t ml[4];
-};
-
-static std::vector<uint32_t> big_mul(std::vector<uint32_t> v, uint32_t x) {
-  uint64_t carry = 0;
-  for (uint32_t& l : v) {
-    const uint64_t t = uint64_t(l) * x + carry;
-    l = uint32_t(t);
-    carry = t >> 32;
-  }
-  if (carry) v.push_back(uint32_t(carry));
-  return v;
-}
-
-static std::vector<uint32_t> big_div(const std::vector<uint32_t>& v, uint32_t x) {  // exact division
-  std::vector<uint32_t> q(v.size());
-  uint64_t rem = 0;
-  for (size_t i = v.size(); i-- > 0;) {
-    const uint64_t cur = (rem << 32) | v[i];
-    q[i] = uint32_t(cur / x);
-    rem = cur % x;
-  }
-  return q;
-}
-
-static uint32_t big_mod(const std::vector<uint32_t>& v, uint32_t x) {
-  uint64_t rem = 0;
-  for (size_t i = v.size(); i-- > 0;) rem = ((rem << 32) | v[i]) % x;
-  return uint32_t(rem);
-}
-
-static double big_double(const std::vector<uint32_t>& v) {
-  long double d = 0.0L;
-  for (size_t i = v.size(); i-- > 0;) d = d * 4294967296.0L + (long double)v[i];
-  return (double)d;
-}
-
-static CrtConsts make_crt_consts(int N) {
-  CrtConsts t{};
-  std::vector<uint32_t> M{1};
-  for (int i = 0; i < N; ++i) M = big_mul(M, uint32_t(kCrtModuli[i]));
-  const long double Md = (long double)big_double(M);
-  for (int j = 0; j < 4; ++j) t.ml[j] = j < (int)M.size() ? M[j] : 0u;
-  for (int i = 0; i < N; ++i) {
-    const uint32_t p = uint32_t(kCrtModuli[i]);
-    const std::vector<uint32_t> Mi = big_div(M, p);
-    const uint32_t a = big_mod(Mi, p);
-    uint32_t inv = 1;  // a^-1 mod p by search (p < 256)
-    while ((uint64_t(a) * inv) % p != 1) ++inv;
-    const std::vector<uint32_t> ci = big_mul(Mi, inv);
-    for (int j = 0; j < 4; ++j) t.cl[i][j] = j < (int)ci.size() ? ci[j] : 0u;
-    t.frac[i] = (double)((long double)big_double(ci) / Md);
-  }
-  return t;
-}
-
-template <int N>
-static hipError_t launch_crt_combine_n(CrtCombineArgs g, hipStream_t st) {
-  const int64_t blocks = g.m * ((g.n + 255) / 256);
-  if (blocks <= 0) return hipSuccess;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  static const CrtConsts k = make_crt_consts(N);
-  std::copy(&k.cl[0][0], &k.cl[0][0] + kMaxCrtModuli * 4, &g.cl[0][0]);
-  std::copy(k.frac, k.frac + kMaxCrtModuli, g.frac);
-  std::copy(k.ml, k.ml + 4, g.ml);
-  hipLaunchKernelGGL((crt_combine<N>), dim3((unsigned)blocks), dim3(256), 0, st, g);
-  return hipGetLastError();
-}
-
-#define BQ_CRT_CASES(X) \
-  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
-
-hipError_t launch_crt_split(int N, const SplitArgs& a, int* exps, void* out, hipStream_t st) {
-#define X(NN) \
-  if (N == NN) return launch_crt_split_n<NN>(a, exps, out, st);
-  BQ_CRT_CASES(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_crt_gemm(int N, const CrtGemmArgs& g, hipStream_t st) {
-  const int64_t tiles = ((g.m + 127) / 128) * ((g.n + 127) / 128);
-  if (tiles <= 0 || N <= 0) return hipSuccess;
-  if (tiles > 0x7fffffff || N > kMaxCrtModuli) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(crt_gemm, dim3((unsigned)tiles, (unsigned)N), dim3(256), 0, st, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_crt_combine(int N, const CrtCombineArgs& g, hipStream_t st) {
-#define X(NN) \
-  if (N == NN) return launch_crt_combine_n<NN>(g, st);
-  BQ_CRT_CASES(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-int crt_modulus(int i) { return (i >= 0 && i < kMaxCrtModuli) ? kCrtModuli[i] : 0; }
 
 int max_slices(int et) { return et == 0 ? 8 : (et == 1 ? 14 : 9); }
 

@@ -199,20 +199,24 @@ def test_create_without_gpu_fails_cleanly():
 @pytest.mark.parametrize("k", [1, 40, 1000, 16384, 70000, 133120])
 def test_crt_workspace_uses_oracle_moduli(k):
     """CRT form: digits are one byte per modulus (rows and columns padded to
-    128, k to 64), plus N residue planes of m x n bytes; N = 0 resolves to
-    the fewest moduli that carry 53 bits for this k, the count the oracle
-    (which checks the modulus product with exact integers) picks."""
+    256, k to 128), plus exponents and N residue planes of m rows of n bytes
+    rounded up to 16 for each of three real products; N = 0 resolves to the fewest moduli that carry 53 bits for this k,
+    the count the oracle (which checks the modulus product with exact
+    integers) picks."""
     from oracle import ozaki2
 
     m, n = 100, 60
     res, mn = ws_need(m, n, k)
     N = ozaki2.default_moduli(k)
     al = lambda x: (x + 255) // 256 * 256
-    kp = (k + 63) // 64 * 64
-    extra = al(N * 128 * kp) + al(N * 128 * kp) + al(128 * 4) + al(128 * 4) + al(N * m * n)
+    kp = (k + 127) // 128 * 128
+    ldr = (n + 15) // 16 * 16
+    # three sets of exponents and residue planes: the real products of one
+    # complex product
+    extra = al(N * 256 * kp) + al(N * 256 * kp) + 3 * (al(256 * 4) + al(256 * 4) + al(N * m * ldr))
     assert B.workspace_size(m, n, k, 0xFF, 0xFF, "split_int8_crt", 0) == (res + extra, mn + extra)
     N2 = max(1, N - 3)
-    extra2 = al(N2 * 128 * kp) * 2 + al(128 * 4) * 2 + al(N2 * m * n)
+    extra2 = al(N2 * 256 * kp) * 2 + 3 * (al(256 * 4) * 2 + al(N2 * m * ldr))
     assert B.workspace_size(m, n, k, 0xFF, 0xFF, "split_int8_crt", N2) == (res + extra2, mn + extra2)
 
 

@@ -46,14 +46,17 @@ def run(bq, A, B, N=0, **kw):
     return C.cpu().numpy()
 
 
+@pytest.mark.parametrize("tile", ["128", "256"])
 @pytest.mark.parametrize("dist", ["uniform", "logspread", "normal"])
 @pytest.mark.parametrize("N", [0, 9, 20])
-def test_real_product_bit_exact(bq, dist, N):
-    """m, k, n = 130, 200, 70 (two 128-row tiles, ragged columns, k three
-    64-steps with a ragged tail): every element equal to the oracle's."""
+def test_real_product_bit_exact(bq, dist, N, tile, monkeypatch):
+    """m, k, n = 300, 200, 70 with either residue-GEMM block: several row
+    tiles with a ragged last one, ragged columns, k two 128-steps with a
+    ragged tail: every element equal to the oracle's."""
+    monkeypatch.setenv("BQ_CRT_TILE", tile)
     R = inputs.MASKS["real"]
-    A, B = inputs.pair(130, 200, 70, dist, seed=60, mask_a=R, mask_b=R)
-    print(f"crt real product {dist} N={N}", flush=True)
+    A, B = inputs.pair(300, 200, 70, dist, seed=60, mask_a=R, mask_b=R)
+    print(f"crt real product {dist} N={N} tile {tile}", flush=True)
     got = run(bq, A, B, N, mask_a=R, mask_b=R)
     assert np.array_equal(got[0], ozaki2.product(A[0], B[0], N))
     assert not np.any(got[1:])
@@ -76,8 +79,10 @@ def test_integer_bit_exact(bq):
     assert np.array_equal(run(bq, A, B), oracle.gemm(A, B))
 
 
+@pytest.mark.parametrize("tile", ["128", "256"])
 @pytest.mark.parametrize("N", [0, 12])
-def test_matches_cpu_split_model(bq, N):
+def test_matches_cpu_split_model(bq, N, tile, monkeypatch):
+    monkeypatch.setenv("BQ_CRT_TILE", tile)
     A, B = inputs.pair(70, 60, 50, "logspread", seed=63)
     print(f"crt N={N} vs model", flush=True)
     ref = bilinear(A, B, Counter(lambda x, y: ozaki2.product(x, y, N)))
@@ -135,13 +140,15 @@ def test_zero_rows_columns_and_degenerate_shapes(bq):
     assert not np.any(run(bq, A0, B0))
 
 
-def test_int32_sums_at_max_k(bq):
+@pytest.mark.parametrize("tile", ["128", "256"])
+def test_int32_sums_at_max_k(bq, tile, monkeypatch):
     """k = 133120, the largest k the form takes: every row of A and column of
     B equals 251/256, whose scaled integer 251 2^45 is 127 modulo 255, so the
     INT8 GEMM of that modulus sums k 127^2 = 2147092480 (just under 2^31).
     The product k (251/256)^2 is exact in FP64."""
     import torch
 
+    monkeypatch.setenv("BQ_CRT_TILE", tile)
     k = 133120
     x = 251.0 / 256.0
     A = torch.zeros((8, 4, k), dtype=torch.float64, device="cuda")
@@ -164,6 +171,7 @@ def _sample(n, r, seed):
 
 @pytest.mark.parametrize("dist", ["uniform", "logspread"])
 def test_n8192_sampled(bq, dist):
+    """Default block choice (256 x 256 at this size)."""
     import torch
 
     n, r = 8192, 48
@@ -205,3 +213,28 @@ def test_real_product_n8192_sampled_bit_exact(bq):
     # and columns carry theirs, so the sampled product is the full product's
     want = ozaki2.product(X, Y, ozaki2.default_moduli(n))
     assert np.array_equal(C[0][ri][:, ci].cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("prec", ["split_int8_crt", "split_int8", "split_bf16", "split_fp8"])
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_non_finite_propagation(bq, prec, bad):
+    """A NaN or infinity in row 11 of A (component 7) and column 5 of B
+    (component 2) makes row 11 and column 5 of every output component NaN,
+    as in the FP64 path (there an infinity can also give +-inf); the rest
+    stays finite and matches the oracle."""
+    import torch
+
+    A, B = inputs.pair(40, 40, 40, "uniform", seed=10)
+    A[6, 11, 3] = bad
+    B[1, 7, 5] = bad
+    C = bq.bq_gemm(torch.from_numpy(A).to("cuda"), torch.from_numpy(B).to("cuda"), prec=prec)
+    torch.cuda.synchronize()
+    C = C.cpu().numpy()
+    assert np.all(np.isnan(C[:, 11, :])) and np.all(np.isnan(C[:, :, 5]))
+    rest = np.delete(np.delete(C, 11, axis=1), 5, axis=2)
+    assert np.all(np.isfinite(rest))
+    A2, B2 = A.copy(), B.copy()
+    A2[6, 11, 3] = 0.0
+    B2[1, 7, 5] = 0.0
+    ref = np.delete(np.delete(oracle.gemm(A2, B2), 11, axis=1), 5, axis=2)
+    assert oracle.rel_frobenius(rest, ref) <= TOL
