@@ -238,3 +238,29 @@ def test_non_finite_propagation(bq, prec, bad):
     B2[1, 7, 5] = 0.0
     ref = np.delete(np.delete(oracle.gemm(A2, B2), 11, axis=1), 5, axis=2)
     assert oracle.rel_frobenius(rest, ref) <= TOL
+
+
+def test_n24576_hermitian_sampled(bq):
+    """n = 24576 in the CRT form (one FP64 block is 4.8 GB > 2^32 bytes, one
+    residue plane 604 MB, the residue GEMM offsets run past 2^32): Fock-like
+    A times density-like B against the oracle on sampled rows and columns
+    that include the last ones."""
+    import torch
+
+    n = 24576
+    print(f"crt n={n}: building Hermitian inputs on the device", flush=True)
+    A, B = inputs.hermitian_pair(n, 3, "cuda")
+    C = bq.bq_gemm(A, B, prec=PREC)
+    torch.cuda.synchronize()
+    print(f"crt n={n}: product done", flush=True)
+    r = 48
+    rows, cols = _sample(n, r, 33), _sample(n, r, 34)
+    ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+    As = A[:, ri, :].cpu().numpy()
+    Bs = B[:, :, ci].cpu().numpy()
+    Cs = C[:, ri][:, :, ci].cpu().numpy()
+    del A, B, C
+    torch.cuda.empty_cache()
+    err = oracle.rel_frobenius(Cs, oracle.gemm(As, Bs))
+    print(f"crt n={n}: sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL
