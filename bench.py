@@ -104,8 +104,9 @@ def heev_leg(bq, inputs, torch, n, log):
     """Diagonalization of a Hermitian biquaternion, n x n (complex order 2n):
     the benchmark's Fock-like generator (U diag(lambda) U^H, known signed
     spectrum 1e0..1e-8), full problem with eigenvectors; then a pure-k input
-    of the same n through the Hadamard-reduced path.  The error is against
-    the generator's known eigenvalues."""
+    of the same n through the Hadamard-reduced path, and a j + k input through
+    the SVD reduction and through the full problem.  The error is against the
+    generator's known eigenvalues."""
     import numpy as np
 
     p = inputs.hermitian_params(n, 7, "fock")
@@ -142,6 +143,22 @@ def heev_leg(bq, inputs, torch, n, log):
                 "reduction_speedup_vs_full": round(ms / ms_k, 2)})
     log(f"heev pure k n={n}: {ms_k:.1f} ms (Hadamard-reduced)")
     del K, w
+    torch.cuda.empty_cache()
+    # j and k together: one SVD of Z12 against the full 2n eigensolve of the same input.
+    JK = torch.from_numpy(inputs.hermitian_random(n, 0xCC, seed=9)).to("cuda")
+    ms_jk, own_jk, w_jk, info_jk = timed(JK, 0xCC)
+    import os
+    os.environ["BQ_HEEV_JK"] = "full"
+    try:
+        ms_jkf, _, w_jkf, _ = timed(JK, 0xCC)
+    finally:
+        del os.environ["BQ_HEEV_JK"]
+    d = float(torch.max(torch.abs(w_jk - w_jkf)).item())
+    out.update({"jk_svd_reduced_ms": round(ms_jk, 2), "jk_full_ms": round(ms_jkf, 2),
+                "jk_svd_speedup_vs_full": round(ms_jkf / ms_jk, 2), "jk_info": info_jk,
+                "jk_max_abs_eigenvalue_diff_svd_vs_full": d})
+    log(f"heev j+k n={n}: SVD-reduced {ms_jk:.1f} ms, full {ms_jkf:.1f} ms, eigenvalue diff {d:.2e}")
+    del JK, w_jk, w_jkf
     torch.cuda.empty_cache()
     return out
 

@@ -221,17 +221,21 @@ bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan);
  *     (c4, c8): Z is block anti-diagonal and the Hadamard-type transform
  *     U = [[I, I], [a I, -a I]] / sqrt(2) (a = i for pure j, a = 1 for pure
  *     k) makes it diag(a Z12, -a Z12): one n x n solve, eigenvalues +-mu;
+ *   - j and k only with both present: with the singular value decomposition
+ *     Z12 = U S V^dagger and G = V U^dagger, U_G = [[I, I], [G, -G]] / sqrt(2)
+ *     makes Z diag(U S U^dagger, -U S U^dagger): one n x n SVD, eigenvalues
+ *     +-s, eigenvectors [u; +-v] / sqrt(2);
  *   - otherwise one 2n x 2n solve.
- * The complex Hermitian eigensolver is rocSOLVER's zheevd (a library call);
- * the mapping, the reduction, the eigenvalue merge and the eigenvector
- * assembly are this library's kernels.
+ * The complex Hermitian eigensolver is rocSOLVER's zheevd and the SVD its
+ * zgesdd (library calls); the mapping, the reduction, the eigenvalue merge
+ * and the eigenvector assembly are this library's kernels.
  *
  * w:    device, 2n doubles: eigenvalues in ascending order.
  * V:    device or NULL: eigenvectors of Z(A) as columns, 2n x 2n complex
  *       (interleaved re, im doubles), column-major with leading dimension
  *       ldv >= 2n complex elements: Z(A) V = V diag(w), V^dagger V = I.
- * info: device int or NULL: 0 on success, > 0 if an eigensolve did not
- *       converge (written asynchronously, like w and V).
+ * info: device int or NULL: 0 on success, > 0 if an eigensolve or the SVD
+ *       did not converge (written asynchronously, like w and V).
  * Only the part of A the isomorph's lower triangle comes from is read; A
  * is taken to be Hermitian, not checked.  n == 0 is a no-op.  Errors as for
  * bq_gemm (validation first, nothing enqueued on error); the workspace is

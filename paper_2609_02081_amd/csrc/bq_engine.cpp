@@ -1550,7 +1550,19 @@ constexpr double kIsoIm[4][8] = {{0, 1, 0, 0, 1, 0, 0, 0},
                                  {0, 0, 0, 1, 0, 0, -1, 0},
                                  {0, -1, 0, 0, 1, 0, 0, 0}};
 
-enum HeevCase { HEEV_FULL, HEEV_BLOCKS, HEEV_BLOCKS_EQUAL, HEEV_BLOCKS_CONJ, HEEV_ANTI_J, HEEV_ANTI_K };
+enum HeevCase { HEEV_FULL, HEEV_BLOCKS, HEEV_BLOCKS_EQUAL, HEEV_BLOCKS_CONJ, HEEV_ANTI_J, HEEV_ANTI_K, HEEV_ANTI_JK };
+
+// Anti-diagonal with j and k together: the singular value decomposition of
+// Z12 (BQ_HEEV_JK=full takes the full problem instead, for comparison), by
+// divide and conquer (BQ_SVD=gesvd: bidiagonal QR).
+bool heev_jk_svd() {
+  const char* e = std::getenv("BQ_HEEV_JK");
+  return !(e && std::strcmp(e, "full") == 0);
+}
+bool heev_use_gesvd() {
+  const char* e = std::getenv("BQ_SVD");
+  return e && std::strcmp(e, "gesvd") == 0;
+}
 
 HeevCase heev_case(unsigned mask) {
   auto has = [&](int c) { return (mask >> c & 1) != 0; };  // c: 0-based component
@@ -1564,14 +1576,15 @@ HeevCase heev_case(unsigned mask) {
   if (!field) {
     if (!has(3) && !has(7)) return HEEV_ANTI_J;  // j only: a = i
     if (!has(2) && !has(6)) return HEEV_ANTI_K;  // k only: a = 1
+    if (heev_jk_svd()) return HEEV_ANTI_JK;      // j and k: SVD of Z12
   }
   return HEEV_FULL;
 }
 
 struct HeevLayout {
-  int64_t order = 0;  // order of each eigensolve
+  int64_t order = 0;  // order of each eigensolve (or of the SVD)
   int solves = 0;
-  size_t z = 0, x1 = 0, x2 = 0, d1 = 0, d2 = 0, e = 0, info = 0, src = 0, scratch = 0;
+  size_t z = 0, x1 = 0, x2 = 0, d1 = 0, d2 = 0, e = 0, info = 0, src = 0, scratch = 0, u = 0, vh = 0;
   size_t scratch_bytes = 0, total = 0;
   bool z_in_ws = false;
 };
@@ -1590,6 +1603,24 @@ bool heev_scratch(rocblas_handle rb, int64_t order, bool vectors, size_t* bytes)
   return rocblas_stop_device_memory_size_query(rb, bytes) == rocblas_status_success;
 }
 
+// The same for the singular value decomposition of one n x n block.
+bool svd_scratch(rocblas_handle rb, int64_t n, bool vectors, size_t* bytes) {
+  *bytes = 0;
+  if (n == 0) return true;
+  if (rocblas_start_device_memory_size_query(rb) != rocblas_status_success) return false;
+  auto* fake_c = reinterpret_cast<rocblas_double_complex*>(uintptr_t(256));
+  auto* fake_d = reinterpret_cast<double*>(uintptr_t(256));
+  auto* fake_i = reinterpret_cast<rocblas_int*>(uintptr_t(256));
+  const rocblas_svect sv = vectors ? rocblas_svect_singular : rocblas_svect_none;
+  const rocblas_int ni = (rocblas_int)n, ld = vectors ? ni : 1;
+  if (heev_use_gesvd())
+    (void)rocsolver_zgesvd(rb, sv, sv, ni, ni, fake_c, ni, fake_d, fake_c, ld, fake_c, ld, fake_d,
+                           rocblas_outofplace, fake_i);
+  else
+    (void)rocsolver_zgesdd(rb, sv, sv, ni, ni, fake_c, ni, fake_d, fake_c, ld, fake_c, ld, fake_i);
+  return rocblas_stop_device_memory_size_query(rb, bytes) == rocblas_status_success;
+}
+
 bool heev_layout(rocblas_handle rb, int64_t n, unsigned mask, bool vectors, HeevLayout* L) {
   const HeevCase hc = heev_case(mask);
   HeevLayout l;
@@ -1605,6 +1636,16 @@ bool heev_layout(rocblas_handle rb, int64_t n, unsigned mask, bool vectors, Heev
     l.solves = 1;
     l.z_in_ws = !vectors;  // with vectors the isomorph is built in V and solved in place
     if (l.z_in_ws) l.z = take(size_t(l.order) * size_t(l.order) * cplx);
+  } else if (hc == HEEV_ANTI_JK) {
+    l.order = n;
+    l.solves = 1;
+    l.x1 = take(size_t(n) * size_t(n) * cplx);
+    l.d1 = take(size_t(n) * 8);
+    if (vectors) {
+      l.u = take(size_t(n) * size_t(n) * cplx);
+      l.vh = take(size_t(n) * size_t(n) * cplx);
+      l.src = take(size_t(2 * n) * 8);
+    }
   } else {
     l.order = n;
     l.solves = hc == HEEV_BLOCKS ? 2 : 1;
@@ -1616,7 +1657,9 @@ bool heev_layout(rocblas_handle rb, int64_t n, unsigned mask, bool vectors, Heev
   }
   l.e = take(size_t(std::max<int64_t>(l.order, 1)) * 8);
   l.info = take(2 * sizeof(int));
-  if (!heev_scratch(rb, l.order, vectors, &l.scratch_bytes)) return false;
+  if (hc == HEEV_ANTI_JK ? !svd_scratch(rb, n, vectors, &l.scratch_bytes)
+                         : !heev_scratch(rb, l.order, vectors, &l.scratch_bytes))
+    return false;
   l.scratch = take(l.scratch_bytes);
   l.total = off;
   *L = l;
@@ -1758,10 +1801,47 @@ bq_status_t bq_heev(bq_handle_t h, const bq_matrix_t* A, double* w, double* V, i
   asmb.V = V;
   asmb.ldv = ldv;
   const double r2 = 1.0 / std::sqrt(2.0);
-  double s2 = 1.0;
+  double s1 = 1.0, s2 = 1.0;
   int rev = 0;
   const double* list2 = nullptr;
-  if (hc == HEEV_ANTI_J || hc == HEEV_ANTI_K) {
+  if (hc == HEEV_ANTI_JK) {
+    // Z = [[0, Z12], [Z12^H, 0]], Z12 = U S V^H: with G = V U^H,
+    // U_G = [[I, I], [G, -G]] / sqrt 2 gives U_G^H Z U_G = diag(U S U^H, -U S U^H),
+    // so the eigenvalues are +-s and the eigenvectors [u; +-v] / sqrt 2.  The
+    // map of the lower block Z21 is read by the solver as Z21^H = Z12 =
+    // Ux S Vx^H, so u = Ux[:, i] and v = Vx[:, i] (row i of Vx^H, conjugated).
+    if ((e = map(2, {1.0, 0.0}, n, X1, n)) != hipSuccess) return hip_fail(e, "reduced block launch");
+    auto* Ux = vectors ? static_cast<double*>(at(L.u)) : nullptr;
+    auto* VxH = vectors ? static_cast<double*>(at(L.vh)) : nullptr;
+    const rocblas_svect sv = vectors ? rocblas_svect_singular : rocblas_svect_none;
+    const rocblas_int ni = (rocblas_int)n, ld = vectors ? ni : 1;
+    auto* Xc = reinterpret_cast<rocblas_double_complex*>(X1);
+    auto* Uc = reinterpret_cast<rocblas_double_complex*>(vectors ? Ux : X1);
+    auto* Vc = reinterpret_cast<rocblas_double_complex*>(vectors ? VxH : X1);
+    {
+      Tracer tr(h, s, BQ_KERNEL_HEEV_SOLVE, vectors ? 3 : 2, n, n, 0, 0.0, 0.0);
+      const rocblas_status rs =
+          heev_use_gesvd() ? rocsolver_zgesvd(h->rb, sv, sv, ni, ni, Xc, ni, D1, Uc, ld, Vc, ld, E, rocblas_outofplace, inf)
+                           : rocsolver_zgesdd(h->rb, sv, sv, ni, ni, Xc, ni, D1, Uc, ld, Vc, ld, inf);
+      tr.done();
+      if (rs != rocblas_status_success)
+        return fail(BQ_ERR_HIP, std::string("rocsolver singular value decomposition: ") + rocblas_status_to_string(rs));
+    }
+    // -s (list 1: S is descending, so -S ascends) and +s (list 2: S reversed).
+    s1 = -1.0;
+    list2 = D1;
+    s2 = 1.0;
+    rev = 1;
+    for (int l = 0; l < 2; ++l) {
+      asmb.xt[l] = Ux;
+      asmb.ct[l][0] = r2;
+      asmb.xb[l] = VxH;
+      asmb.rows_b[l] = 1;
+      asmb.conj_b[l] = 1;
+      asmb.cb[l][0] = l == 0 ? -r2 : r2;
+    }
+    asmb.rev2 = 1;
+  } else if (hc == HEEV_ANTI_J || hc == HEEV_ANTI_K) {
     // U^dagger Z U = diag(a Z12, -a Z12) with U = [[I, I], [a I, -a I]] / sqrt(2).
     const Cplx a = hc == HEEV_ANTI_J ? Cplx{0.0, 1.0} : Cplx{1.0, 0.0};
     if ((e = map(1, a, n, X1, n)) != hipSuccess) return hip_fail(e, "reduced block launch");
@@ -1797,7 +1877,7 @@ bq_status_t bq_heev(bq_handle_t h, const bq_matrix_t* A, double* w, double* V, i
   {
     Tracer tr(h, s, BQ_KERNEL_HEEV_ASSEMBLE, -1, N, vectors ? N : 0, 0, 0.0,
               double(N) * 24.0 + (vectors ? double(N) * double(N) * 16.0 * 2.0 : 0.0));
-    e = bq::launch_heev_merge(D1, n, list2, n, s2, rev, w, src, s);
+    e = bq::launch_heev_merge(D1, n, s1, list2, n, s2, rev, w, src, s);
     if (e == hipSuccess && vectors) e = bq::launch_heev_assemble(asmb, s);
     tr.done();
     if (e != hipSuccess) return hip_fail(e, "eigenvalue merge / vector assembly launch");

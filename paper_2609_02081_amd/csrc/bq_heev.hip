@@ -2,7 +2,8 @@
 // isomorph of eq. mapping-formulas (or one of its blocks, for the reduced
 // problems of the Hadamard transformation for diagonalization), the merge of
 // two ascending eigenvalue lists, and the eigenvector assembly.  The
-// eigensolves themselves are rocSOLVER calls made by the engine.
+// eigensolves and singular value decompositions themselves are rocSOLVER
+// calls made by the engine.
 #include "bq_internal.h"
 
 namespace bq {
@@ -37,11 +38,11 @@ __global__ void __launch_bounds__(256) heev_map_kernel(const HeevMapArgs a) {
   o[1] = -im;
 }
 
-// Ascending merge of list 1 (x1[0..n1), ascending) and list 2 (y2[j] =
-// s2 * x2[rev ? n2 - 1 - j : j], ascending).  Element i of list 1 goes to
-// rank i + #{j : y2[j] < x1[i]}, element j of list 2 to j + #{i : x1[i] <=
-// y2[j]}: every rank is taken once, ties keep list 1 first.  src[rank] = i
-// (list 1) or n1 + j (list 2).
+// Ascending merge of list 1 (y1[i] = s1 * x1[i], ascending) and list 2
+// (y2[j] = s2 * x2[rev ? n2 - 1 - j : j], ascending).  Element i of list 1
+// goes to rank i + #{j : y2[j] < y1[i]}, element j of list 2 to
+// j + #{i : y1[i] <= y2[j]}: every rank is taken once, ties keep list 1
+// first.  src[rank] = i (list 1) or n1 + j (list 2).
 __device__ __forceinline__ int64_t count_less(const double* x, int64_t n, double s, int rev, double v, bool or_equal) {
   int64_t lo = 0, hi = n;  // first index whose value is > v (or >= v)
   while (lo < hi) {
@@ -53,18 +54,18 @@ __device__ __forceinline__ int64_t count_less(const double* x, int64_t n, double
   return lo;
 }
 
-__global__ void __launch_bounds__(256) heev_merge_kernel(const double* x1, int64_t n1, const double* x2, int64_t n2,
-                                                         double s2, int rev, double* w, int64_t* src) {
+__global__ void __launch_bounds__(256) heev_merge_kernel(const double* x1, int64_t n1, double s1, const double* x2,
+                                                         int64_t n2, double s2, int rev, double* w, int64_t* src) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t < n1) {
-    const double v = x1[t];
+    const double v = s1 * x1[t];
     const int64_t rank = t + count_less(x2, n2, s2, rev, v, false);
     w[rank] = v;
     if (src) src[rank] = t;
   } else if (t < n1 + n2) {
     const int64_t j = t - n1;
     const double v = s2 * x2[rev ? n2 - 1 - j : j];
-    const int64_t rank = j + count_less(x1, n1, 1.0, 0, v, true);
+    const int64_t rank = j + count_less(x1, n1, s1, 0, v, true);
     w[rank] = v;
     if (src) src[rank] = t;
   }
@@ -73,8 +74,9 @@ __global__ void __launch_bounds__(256) heev_merge_kernel(const double* x1, int64
 // V (2n x 2n complex, column-major, leading dimension ldv): column o takes
 // list l = (src[o] >= n) and its index; list 2 indexes run reversed when
 // rev2.  Rows 0..n-1 are ct[l] * (conj_t[l] ? conj : id)(xt[l][:, col]),
-// rows n..2n-1 likewise from xb[l]; a null matrix gives zeros.  X matrices
-// are the eigensolver's: column-major n x n complex, leading dimension ldx.
+// or of row col of xt[l] when rows_t[l]; rows n..2n-1 likewise from xb[l];
+// a null matrix gives zeros.  X matrices are the solver's: column-major
+// n x n complex, leading dimension ldx.
 __global__ void __launch_bounds__(256) heev_assemble_kernel(const HeevAsmArgs a) {
   const int64_t N = 2 * a.n;
   const int64_t bpc = (N + 255) / 256;
@@ -90,7 +92,8 @@ __global__ void __launch_bounds__(256) heev_assemble_kernel(const HeevAsmArgs a)
   const double* X = top ? a.xt[l] : a.xb[l];
   double re = 0.0, im = 0.0;
   if (X) {
-    const double* x = X + 2 * (col * a.ldx + rr);
+    const int by_rows = top ? a.rows_t[l] : a.rows_b[l];
+    const double* x = X + 2 * (by_rows ? rr * a.ldx + col : col * a.ldx + rr);
     const double xr = x[0];
     const double xi = (top ? a.conj_t[l] : a.conj_b[l]) ? -x[1] : x[1];
     const double cr = top ? a.ct[l][0] : a.cb[l][0];
@@ -119,13 +122,14 @@ hipError_t launch_heev_map(const HeevMapArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_heev_merge(const double* x1, int64_t n1, const double* x2, int64_t n2, double s2, int rev,
+hipError_t launch_heev_merge(const double* x1, int64_t n1, double s1, const double* x2, int64_t n2, double s2, int rev,
                              double* w, int64_t* src, hipStream_t s) {
   const int64_t total = n1 + n2;
   if (total <= 0) return hipSuccess;
   const int64_t blocks = (total + 255) / 256;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(heev_merge_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x1, n1, x2, n2, s2, rev, w, src);
+  hipLaunchKernelGGL(heev_merge_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x1, n1, s1, x2, n2, s2, rev, w,
+                     src);
   return hipGetLastError();
 }
 

@@ -166,6 +166,7 @@ struct HeevAsmArgs {
   int64_t ldx;
   double ct[2][2], cb[2][2];  // complex coefficients (re, im)
   int conj_t[2], conj_b[2];
+  int rows_t[2], rows_b[2];   // vector j is row j of the source (not column j)
   const int64_t* src;
   int rev2;
   double* V;
@@ -209,7 +210,7 @@ hipError_t launch_crt_combine(int N, const CrtCombineArgs& g, hipStream_t s);
 int crt_modulus(int i);
 // Hermitian eigenproblem kernels (bq_heev.hip).
 hipError_t launch_heev_map(const HeevMapArgs& a, hipStream_t s);
-hipError_t launch_heev_merge(const double* x1, int64_t n1, const double* x2, int64_t n2, double s2, int rev,
+hipError_t launch_heev_merge(const double* x1, int64_t n1, double s1, const double* x2, int64_t n2, double s2, int rev,
                              double* w, int64_t* src, hipStream_t s);
 hipError_t launch_heev_assemble(const HeevAsmArgs& a, hipStream_t s);
 hipError_t launch_heev_info(const int* a, const int* b, int* out, hipStream_t s);

@@ -7,7 +7,8 @@ are checked for what is unique: the residual ||Z V - V diag(w)||_F <=
 1e-12 ||Z||_2 sqrt(2n) and orthonormality max |V^H V - I| <= 1e-12, with Z
 the oracle's isomorph.  Every structure path: full, block diagonal (two
 solves, equal blocks, conjugate blocks), block anti-diagonal (pure j, pure
-k) and the mixed j + k case that falls back to the full problem.
+k) and the j + k anti-diagonal case through the singular value decomposition of
+Z12, and a mixed case that takes the full problem.
 """
 import numpy as np
 import pytest
@@ -26,7 +27,9 @@ CASES = {
     "blocks_conj": 0x03,   # c1, c2: Z22 = conj(Z11)
     "anti_j": 0x44,        # c3, c7: Hadamard transform with a = i
     "anti_k": 0x88,        # c4, c8: a = 1
-    "anti_jk": 0xCC,       # j and k: full problem
+    "anti_jk": 0xCC,       # j and k: SVD of Z12
+    "anti_jk_3": 0x4C,     # c3, c4, c7: SVD of Z12
+    "anti_jk_4": 0x86,     # c2, c3, c8: field unit present, full problem
 }
 
 
@@ -168,3 +171,24 @@ def test_strided_input_and_output(bq, case):
     Vfull = Vt.cpu().numpy()
     assert np.all(Vfull[:, 2 * n:] == 9.0)
     check(A, w.cpu().numpy(), Vfull[:, :2 * n].T)
+
+
+@pytest.mark.parametrize("n", [64, 300])
+def test_jk_svd_matches_full_problem(bq, n, monkeypatch):
+    """The SVD reduction (both rocSOLVER SVD routines) and the full 2n
+    eigensolve of the same j + k input agree on the eigenvalues, and both
+    pass the residual and orthonormality checks."""
+    A = inputs.hermitian_random(n, 0xCC, seed=60 + n)
+    w0, V0, i0 = solve(bq, A, 0xCC)
+    assert i0 == 0
+    check(A, w0, V0)
+    monkeypatch.setenv("BQ_SVD", "gesvd")
+    w1, V1, i1 = solve(bq, A, 0xCC)
+    assert i1 == 0
+    check(A, w1, V1)
+    monkeypatch.delenv("BQ_SVD")
+    monkeypatch.setenv("BQ_HEEV_JK", "full")
+    w2, V2, i2 = solve(bq, A, 0xCC)
+    assert i2 == 0
+    scale = max(1.0, float(np.max(np.abs(w2))))
+    assert np.max(np.abs(w0 - w2)) <= TOL * scale and np.max(np.abs(w1 - w2)) <= TOL * scale
