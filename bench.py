@@ -347,9 +347,25 @@ def main():
                 "kernel": "cgemm_f64<GAUSS> (one complex product, 3 real FP64 GEMMs)",
                 "launches": len(gemm), "avg_launch_ms": round(g_ms, 3),
                 "flops_per_launch": g_flops}
+    # A plain device-to-device copy of 4 GiB (read + write), the rate a
+    # streaming kernel can reach on this machine, beside the combination pass.
+    cp_src = torch.empty(1 << 29, dtype=torch.float64, device=dev)
+    cp_dst = torch.empty_like(cp_src)
+    cp_dst.copy_(cp_src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        cp_dst.copy_(cp_src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 2.0 * cp_src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del cp_src, cp_dst
+    torch.cuda.empty_cache()
     combine = {"bound": "hbm", "avg_launch_ms": round(c_ms, 4), "bytes_per_launch": c_bytes,
                "achieved_GBs": round(c_bytes / (c_ms * 1e-3) / 1e9, 1) if c_ms > 0 else None,
-               "peak_GBs": PEAK_HBM_GBS, "launches": len(comb)}
+               "peak_GBs": PEAK_HBM_GBS, "launches": len(comb),
+               "device_copy_GBs": round(copy_gbs, 1)}
 
     # Sampled sub-block (rows R, columns S, the last row and column always
     # included) of every result, for the CPU baseline leg below.

@@ -337,24 +337,35 @@ cgemm_f64(const GemmArgs g) {
 // Hadamard pre-combination.  One thread produces two adjacent columns of
 // every requested combination.
 // ---------------------------------------------------------------------------
+// 2 columns per thread; VEC = 1 (every pointer 16-byte aligned, both
+// leading dimensions even): one 16-byte load per source and one 16-byte
+// store per destination, else element by element.
+template <int VEC>
 __global__ void __launch_bounds__(256) combine_kernel(const CombineArgs a) {
-  const int64_t cpairs = (a.cols + 1) / 2;
-  const int64_t bpr = (cpairs + 255) / 256;
+  constexpr int CPT = 2;  // columns per thread
+  const int64_t cgroups = (a.cols + CPT - 1) / CPT;
+  const int64_t bpr = (cgroups + 255) / 256;
   const int64_t row = blockIdx.x / bpr;
-  const int64_t c = ((blockIdx.x % bpr) * 256 + threadIdx.x) * 2;
+  const int64_t c = ((blockIdx.x % bpr) * 256 + threadIdx.x) * CPT;
   if (row >= a.rows || c >= a.cols) return;
-  const bool two = (c + 1 < a.cols);
-  double x[8][2];
+  const bool full = (c + CPT <= a.cols);
+  double x[8][CPT];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const double* s = a.src[u];
     if (s) {
       const double* p = s + row * a.lds + c;
-      x[u][0] = p[0];
-      x[u][1] = two ? p[1] : 0.0;
+      if (VEC && full) {
+        const double2 v2 = *reinterpret_cast<const double2*>(p);
+        x[u][0] = v2.x;
+        x[u][1] = v2.y;
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) x[u][t] = (c + t < a.cols) ? p[t] : 0.0;
+      }
     } else {
-      x[u][0] = 0.0;
-      x[u][1] = 0.0;
+#pragma unroll
+      for (int t = 0; t < CPT; ++t) x[u][t] = 0.0;
     }
   }
   for (int q = 0; q < a.nq; ++q) {
@@ -363,16 +374,21 @@ __global__ void __launch_bounds__(256) combine_kernel(const CombineArgs a) {
       double* d = (h == 0) ? a.dst_r[q] : a.dst_i[q];
       if (!d) continue;
       const int o = 4 * h;
-      double v0 = a.w[q][0] * x[o][0];
-      double v1 = a.w[q][0] * x[o][1];
+      double v[CPT];
 #pragma unroll
-      for (int u = 1; u < 4; ++u) {
-        v0 = v0 + a.w[q][u] * x[o + u][0];
-        v1 = v1 + a.w[q][u] * x[o + u][1];
+      for (int t = 0; t < CPT; ++t) {
+        v[t] = a.w[q][0] * x[o][t];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) v[t] = v[t] + a.w[q][u] * x[o + u][t];
       }
       double* p = d + row * a.ldd + c;
-      p[0] = v0;
-      if (two) p[1] = v1;
+      if (VEC && full) {
+        *reinterpret_cast<double2*>(p) = double2{v[0], v[1]};
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t)
+          if (c + t < a.cols) p[t] = v[t];
+      }
     }
   }
 }
@@ -570,10 +586,15 @@ hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_pr
 
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s) {
   if (a.rows <= 0 || a.cols <= 0) return hipSuccess;
+  auto al16 = [](const double* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+  bool vec = (a.lds % 2 == 0) && (a.ldd % 2 == 0);
+  for (int u = 0; u < 8; ++u) vec = vec && al16(a.src[u]);
+  for (int q = 0; q < a.nq; ++q) vec = vec && al16(a.dst_r[q]) && al16(a.dst_i[q]);
   const int64_t bpr = ((a.cols + 1) / 2 + 255) / 256;
   const int64_t blocks = bpr * a.rows;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (vec) hipLaunchKernelGGL(combine_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(combine_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
