@@ -174,7 +174,8 @@ int bq_plan_real_gemms(unsigned maskA, unsigned maskB);
  * Pointers in the problems are baked into the plan: A, B, C of every problem
  * must stay valid (and C must not overlap any A, B or other C) until the
  * plan is destroyed.  FP64 plans need full biquaternions (all 16 input
- * components present) and op N or C; others return BQ_ERR_UNSUPPORTED.
+ * components present); others return BQ_ERR_UNSUPPORTED.  Every op is
+ * taken, per problem (T and H read the stored matrices, as in bq_gemm).
  * Plan creation allocates the plan's device tables (hipMalloc, once);
  * launching allocates nothing.  A plan is bound to the workspace pointer of
  * its first launch: a later launch with another pointer re-records the graph.

@@ -302,7 +302,8 @@ def trace_read(device: int = 0, cap: int = 4096) -> list[dict]:
 
 
 class GroupedPlan:
-    """Batched plan over (A, B, C) triples of (8, rows, cols) device tensors.
+    """Batched plan over (A, B, C) triples of (8, rows, cols) device tensors,
+    or (A, B, C, opA, opB) for per-problem ops (else opA, opB apply to all).
 
     The tensors are referenced by the plan and must stay alive (this object
     keeps them) until close().  Workspace comes from torch unless given."""
@@ -310,8 +311,10 @@ class GroupedPlan:
     def __init__(self, problems, prec="fp64", slices=0, opA="N", opB="N", device=0):
         self._keep = []
         arr = (BqProblem * max(1, len(problems)))()
-        for i, (A, B, C) in enumerate(problems):
-            arr[i].opA, arr[i].opB = OPS[opA], OPS[opB]
+        for i, prob in enumerate(problems):
+            A, B, C = prob[:3]
+            oa, ob = (prob[3], prob[4]) if len(prob) == 5 else (opA, opB)
+            arr[i].opA, arr[i].opB = OPS[oa], OPS[ob]
             arr[i].A, arr[i].B, arr[i].C = matrix(A), matrix(B), matrix(C)
             self._keep.append((A, B, C))
         self.device = device

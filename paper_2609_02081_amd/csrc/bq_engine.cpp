@@ -1182,9 +1182,9 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
     for (int pi = 0; pi < p->count; ++pi) {
       const bq_problem_t& q = p->probs[pi];
       const Plan& pl = p->plans[pi];
-      const int64_t m = pl.m, n = pl.n, k = pl.k;  // op N or C: the stored shapes
+      const int64_t m = pl.m, n = pl.n, k = pl.k;  // shapes of op(A), op(B)
       char* wp = static_cast<char*>(ws) + p->ws_off[pi];
-      const int64_t kpad = round_up(k, 8), npad = round_up(n, 8);
+      const int64_t kpad = round_up(k, 8), npad = round_up(n, 8), mpad = round_up(m, 8);
       const size_t a1 = align256(combo_slot_bytes(m, k)), b1 = align256(combo_slot_bytes(k, n));
       double *cAr[4], *cAi[4], *cBr[4], *cBi[4];
       for (int c = 0; c < 4; ++c) {
@@ -1198,9 +1198,9 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
         const bq_matrix_t& X = side == 0 ? q.A : q.B;
         for (int c = 0; c < 8; ++c) ca.src[c] = X.comp[c];
         ca.lds = X.ld;
-        ca.rows = side == 0 ? m : k;
-        ca.cols = side == 0 ? k : n;
-        ca.ldd = side == 0 ? kpad : npad;
+        ca.rows = X.rows;  // the stored orientation (op T / H keep it)
+        ca.cols = X.cols;
+        ca.ldd = side == 0 ? (pl.ta ? mpad : kpad) : (pl.tb ? kpad : npad);
         ca.nq = 4;
         for (int j = 0; j < 4; ++j) {
           ca.dst_r[j] = side == 0 ? cAr[j] : cBr[j];
@@ -1216,13 +1216,14 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
       for (const Prod& pd : pl.prods) {
         Operand L = pd.L, R = pd.R;
         if (L.combo >= 0) {
-          L.r = cAr[L.combo]; L.i = cAi[L.combo]; L.ld = kpad;
-          R.r = cBr[R.combo]; R.i = cBi[R.combo]; R.ld = npad;
+          L.r = cAr[L.combo]; L.i = cAi[L.combo]; L.ld = pl.ta ? mpad : kpad;
+          R.r = cBr[R.combo]; R.i = cBi[R.combo]; R.ld = pl.tb ? kpad : npad;
         }
         bq::GemmArgs g{};
         g.lr = L.r; g.li = L.i; g.lda = L.ld;
         g.rr = R.r; g.ri = R.i; g.ldb = R.ld;
         g.m = m; g.n = n; g.k = k;
+        g.ta = pl.ta; g.tb = pl.tb;
         g.sL = L.s; g.sR = R.s;
         g.ldc = q.C.ld;
         g.xcd_remap = 0;
@@ -1319,8 +1320,6 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
     if (st != BQ_OK) return fail(st, "problem " + std::to_string(i) + ": " + g_detail);
     const int64_t m = pl.m, n = pl.n, k = pl.k;
     if (pr.et < 0) {
-      if (op_trans(q.opA) || op_trans(q.opB))
-        return fail(BQ_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": FP64 batched plans take op N or C");
       for (int c = 0; c < 8; ++c)
         if (!q.A.comp[c] || !q.B.comp[c])
           return fail(BQ_ERR_UNSUPPORTED, "problem " + std::to_string(i) +
@@ -1408,9 +1407,8 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
   if (e == hipSuccess && pr.et < 0 && count > 0) {
     std::vector<bq::GroupedItem> items;
     for (int i : p->order) {
-      const bq_problem_t& q = p->probs[i];
-      const int tm = int((q.A.rows + kGroupedTile - 1) / kGroupedTile);
-      const int tn = int((q.B.cols + kGroupedTile - 1) / kGroupedTile);
+      const int tm = int((p->plans[i].m + kGroupedTile - 1) / kGroupedTile);
+      const int tn = int((p->plans[i].n + kGroupedTile - 1) / kGroupedTile);
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) items.push_back({i * 8, int(p->plans[i].prods.size()), a, b});
     }

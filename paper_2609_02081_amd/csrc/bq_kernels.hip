@@ -482,7 +482,15 @@ grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* c
     const GroupedItem w = items[it];
     for (int q = 0; q < w.nprod; ++q) {
       const GemmArgs g = prods[w.prod0 + q];
-      gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN>(g, (int64_t)w.tm * BM, (int64_t)w.tn * BN, sm);
+      const int64_t m0 = (int64_t)w.tm * BM, n0 = (int64_t)w.tn * BN;
+      // op T / H operands are read in their stored orientation
+      if (g.ta) {
+        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 1>(g, m0, n0, sm);
+        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 0>(g, m0, n0, sm);
+      } else {
+        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 1>(g, m0, n0, sm);
+        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 0>(g, m0, n0, sm);
+      }
     }
     if (!DYN) it += gridDim.x;
   }

@@ -62,6 +62,37 @@ def test_small_batch_matches_oracle_and_single_calls(bq):
     plan.close()
 
 
+OP_FN = {"N": lambda M: M, "T": oracle.transpose, "C": oracle.conj, "H": oracle.herm}
+
+
+def test_mixed_ops_batch(bq):
+    """All 16 op pairs in one FP64 plan, one per problem (T and H read the
+    stored matrices: A stored k x m, B stored n x k), ragged shapes: each
+    product against the oracle and against the single call."""
+    import torch
+
+    rng = np.random.default_rng(62)
+    pairs = [(a, b) for a in "NTCH" for b in "NTCH"]
+    probs, shapes = [], []
+    for idx, (oa, ob) in enumerate(pairs):
+        m, k, n = SMALL[idx % len(SMALL)]
+        A = torch.from_numpy(inputs.blocks(rng, *((k, m) if oa in "TH" else (m, k)))).to("cuda")
+        B = torch.from_numpy(inputs.blocks(rng, *((n, k) if ob in "TH" else (k, n)))).to("cuda")
+        C = torch.full((8, m, n), float("nan"), dtype=torch.float64, device="cuda")
+        probs.append((A, B, C, oa, ob))
+        shapes.append((m, k, n))
+    plan = bq.GroupedPlan(probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (A, B, C, oa, ob), shape in zip(probs, shapes):
+        ref = oracle.gemm(OP_FN[oa](A.cpu().numpy()), OP_FN[ob](B.cpu().numpy()))
+        assert oracle.rel_frobenius(C.cpu().numpy(), ref) <= TOL, (oa, ob, shape)
+        single = bq.bq_gemm(A, B, opA=oa, opB=ob)
+        torch.cuda.synchronize()
+        assert oracle.rel_frobenius(C.cpu().numpy(), single.cpu().numpy()) <= 1e-15, (oa, ob, shape)
+    plan.close()
+
+
 def test_replays_identical_with_eager_work_between(bq):
     import torch
 
