@@ -65,8 +65,9 @@ def test_small_batch_matches_oracle_and_single_calls(bq):
 OP_FN = {"N": lambda M: M, "T": oracle.transpose, "C": oracle.conj, "H": oracle.herm}
 
 
-def test_mixed_ops_batch(bq):
-    """All 16 op pairs in one FP64 plan, one per problem (T and H read the
+@pytest.mark.parametrize("prec", ["fp64", "split_int8_crt"])
+def test_mixed_ops_batch(bq, prec):
+    """All 16 op pairs in one plan, one per problem (T and H read the
     stored matrices: A stored k x m, B stored n x k), ragged shapes: each
     product against the oracle and against the single call."""
     import torch
@@ -81,13 +82,13 @@ def test_mixed_ops_batch(bq):
         C = torch.full((8, m, n), float("nan"), dtype=torch.float64, device="cuda")
         probs.append((A, B, C, oa, ob))
         shapes.append((m, k, n))
-    plan = bq.GroupedPlan(probs)
+    plan = bq.GroupedPlan(probs, prec=prec)
     plan.launch()
     torch.cuda.synchronize()
     for (A, B, C, oa, ob), shape in zip(probs, shapes):
         ref = oracle.gemm(OP_FN[oa](A.cpu().numpy()), OP_FN[ob](B.cpu().numpy()))
         assert oracle.rel_frobenius(C.cpu().numpy(), ref) <= TOL, (oa, ob, shape)
-        single = bq.bq_gemm(A, B, opA=oa, opB=ob)
+        single = bq.bq_gemm(A, B, opA=oa, opB=ob, prec=prec)
         torch.cuda.synchronize()
         assert oracle.rel_frobenius(C.cpu().numpy(), single.cpu().numpy()) <= 1e-15, (oa, ob, shape)
     plan.close()
