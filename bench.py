@@ -100,6 +100,61 @@ def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, copy_bytes
     print(json.dumps(out))
 
 
+class SmiSampler:
+    """Socket power and graphics clocks sampled with `amd-smi metric -p -c`
+    (a child process, about every half second) while a region runs.  None
+    if the tool is missing or fails; it never affects the timed work."""
+
+    def __init__(self, interval=0.5):
+        import shutil
+        import threading
+
+        self.exe = shutil.which("amd-smi") or ("/opt/rocm/bin/amd-smi" if os.path.exists("/opt/rocm/bin/amd-smi")
+                                               else None)
+        self.interval = interval
+        self.samples = []
+        self._stop = threading.Event()
+        self._thread = threading.Thread(target=self._run, daemon=True)
+
+    def _one(self):
+        import subprocess
+
+        out = subprocess.run([self.exe, "metric", "-p", "-c", "--json"], capture_output=True, text=True,
+                             timeout=10).stdout
+        g = json.loads(out)["gpu_data"][0]
+        clocks = [v["clk"]["value"] for k, v in g["clock"].items()
+                  if k.startswith("gfx_") and isinstance(v, dict) and isinstance(v.get("clk"), dict)]
+        return float(g["power"]["socket_power"]["value"]), (sum(clocks) / len(clocks) if clocks else None)
+
+    def _run(self):
+        while not self._stop.is_set():
+            try:
+                self.samples.append(self._one())
+            except Exception:
+                return
+            self._stop.wait(self.interval)
+
+    def __enter__(self):
+        if self.exe:
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self._thread.is_alive():
+            self._thread.join(timeout=15)
+        return False
+
+    def summary(self):
+        pw = [p for p, _ in self.samples]
+        ck = [c for _, c in self.samples if c is not None]
+        if not pw:
+            return None
+        return {"samples": len(pw), "socket_power_W_mean": round(sum(pw) / len(pw), 1),
+                "socket_power_W_max": max(pw), "gfx_clock_MHz_mean": round(sum(ck) / len(ck), 1) if ck else None,
+                "gfx_clock_MHz_min": min(ck) if ck else None, "tool": "amd-smi metric -p -c"}
+
+
 def paper_like_leg(bq, inputs, torch, n, log):
     """The product timed the way the paper times its GPU runs: inputs in host
     memory (pinned), copied to the device, multiplied, the result copied
@@ -370,15 +425,16 @@ def main():
     bq.trace_enable(True)
     bq.trace_read()
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    ev0.record(stream)
-    for i in range(args.steps):
-        bq.bq_gemm(A, B, C, workspace=ws)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
+    with SmiSampler() as smi_fp64:
+        evs[0].record(stream)
+        for i in range(args.steps):
+            bq.bq_gemm(A, B, C, workspace=ws)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+    total_ms = evs[0].elapsed_time(evs[-1])
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
     recs = bq.trace_read()
     log(f"timed {args.steps} steps: {total_ms:.1f} ms")
 
@@ -422,6 +478,29 @@ def main():
                "peak_GBs": PEAK_HBM_GBS, "launches": len(comb),
                "device_copy_GBs": round(copy_gbs, 1)}
 
+    # One GPU's share of the 8-GPU row-slab sharding: rows [0, n/8) of A and
+    # C (views, so no new memory) times the whole B.
+    slab = None
+    if n % 8 == 0:
+        ms_ = n // 8
+        As, Cs = A[:, :ms_, :], C[:, :ms_, :]
+        bq.bq_gemm(As, B, Cs, workspace=ws)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            bq.bq_gemm(As, B, Cs, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sl_ms = e0.elapsed_time(e1) / 3
+        bq.trace_read()
+        slab = {"shape": f"{ms_} x {n} x {n} (rows of A and C one of 8 GPUs would own)", "ms": round(sl_ms, 2),
+                "eff_tflops": round(64 * 2.0 * ms_ * n * n / (sl_ms * 1e-3) / 1e12, 2)}
+        log(f"slab {ms_}x{n}x{n}: {sl_ms:.1f} ms")
+        # (rows [0, n/8) of C now hold the slab products: the same product, so
+        # the samples below still check C = A B)
+
     # Sampled sub-block (rows R, columns S, the last row and column always
     # included) of every result, for the CPU baseline leg below.
     r = args.cpu_sample
@@ -454,10 +533,11 @@ def main():
                 bq.trace_read()
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                bq.bq_gemm(A, B, C, prec=prec, slices=S, workspace=sws)
-                e1.record(stream)
-                torch.cuda.synchronize()
+                with SmiSampler() as smi_split:
+                    e0.record(stream)
+                    bq.bq_gemm(A, B, C, prec=prec, slices=S, workspace=sws)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
                 sms = e0.elapsed_time(e1)
                 srecs = bq.trace_read()
                 del sws
@@ -481,6 +561,7 @@ def main():
                            if sg_ms > 0 else None,
                            "split_kernels_ms": round(sum(x["ms"] for x in srecs if x["kernel"] == "split"), 2),
                            "crt_combine_ms": round(sum(x["ms"] for x in srecs if x["kernel"] == "crt_combine"), 2),
+                           "power_clock": smi_split.summary(),
                            "tried": tried}
             if r > 0:
                 samples[prec] = cs
@@ -559,6 +640,8 @@ def main():
 
     out = {"metric": METRIC, "value": round(eff_tflops, 3), "unit": "effective TFLOP/s (64 real GEMMs counted)",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "ms_per_step_min": round(step_ms[0], 3), "ms_per_step_median": round(step_ms[len(step_ms) // 2], 3),
+           "power_clock": smi_fp64.summary(),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": f"biquaternion GEMM C=A.B, n={n}, A Fock-like x B density-like "
@@ -569,7 +652,7 @@ def main():
            "rel_err_sampled_vs_oracle": rel_err,
            "roofline": roofline, "combine": combine, "cpu_baseline": cpu,
            "split_precision": split, "op_pairs": ops, "batched": batched, "diagonalization": heev,
-           "paper_like": paper_like}
+           "slab_one_of_8": slab, "paper_like": paper_like}
     print(json.dumps(out), flush=True)
 
 
