@@ -59,8 +59,12 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 //   B (4x16):  lane l holds B[l / 16][l % 16]
 //   D (16x16): lane l, element v holds D[l / 16 + 4 v][l % 16]
 // (the D layout was checked on gfx950 with a one-wave probe).
-// LDS keeps the A tile k-major (As[k][i]) and the B tile as stored
-// (Bs[k][j]) so both fragment reads are 16 consecutive doubles per k row.
+// LDS keeps the B tile as stored (Bs[k][j]), so a fragment read is 16
+// consecutive doubles per k row.  The A tile is kept row-major with rows of
+// BK + 1 doubles (As[i][k]): its rows are written as loaded, without the
+// bank conflicts of a transposing write, and the 16 rows of a fragment read
+// fall on 16 distinct bank pairs.  A stored transposed (op T, H) arrives
+// k-major and is kept so (As[k][i], rows of BM + PAD).
 // ---------------------------------------------------------------------------
 // LDS of one FP64 GEMM tile (double-buffered A and B tiles).
 template <int KIND, int BM, int BN, int BK>
@@ -68,7 +72,10 @@ struct TileSmem {
   static constexpr int PAD = 4;
   static constexpr int NA = (KIND == KIND_GAUSS || KIND == KIND_CR) ? 2 : 1;
   static constexpr int NB = (KIND == KIND_GAUSS || KIND == KIND_RC) ? 2 : 1;
-  __attribute__((aligned(16))) double As[2][NA][BK][BM + PAD];
+  static constexpr int A_KM = BK * (BM + PAD), A_MM = BM * (BK + 1);
+  static constexpr int A_SIZE = A_KM > A_MM ? A_KM : A_MM;
+  static_assert(A_SIZE % 2 == 0, "buffers stay 16-byte aligned");
+  __attribute__((aligned(16))) double As[2][NA][A_SIZE];
   __attribute__((aligned(16))) double Bs[2][NB][BK][BN + PAD];
 };
 
@@ -125,9 +132,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   static_assert(BK % 4 == 0 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
   static_assert(((BN + PAD) * 8) % 16 == 0 && ((BM + PAD) * 8) % 16 == 0, "LDS rows must stay 16-byte aligned");
 
-  // Double-buffered LDS, both tiles k-major: As[k][i], Bs[k][j].
+  // Double-buffered LDS: A row-major with rows of BK + 1 (TA: k-major with
+  // rows of BM + PAD), B k-major.
   auto& As = sm.As;
   auto& Bs = sm.Bs;
+  auto a_at = [](int i, int k) { return TA ? k * (BM + PAD) + i : i * (BK + 1) + k; };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -191,10 +200,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
       for (int p = 0; p < NA; ++p) {
         if constexpr (TA) {
-          *reinterpret_cast<d2*>(&As[buf][p][r][c]) = d2{ra[p][2 * i], ra[p][2 * i + 1]};
+          *reinterpret_cast<d2*>(&As[buf][p][a_at(c, r)]) = d2{ra[p][2 * i], ra[p][2 * i + 1]};
         } else {
-          As[buf][p][c][r] = ra[p][2 * i];
-          As[buf][p][c + 1][r] = ra[p][2 * i + 1];
+          As[buf][p][a_at(r, c)] = ra[p][2 * i];
+          As[buf][p][a_at(r, c) + 1] = ra[p][2 * i + 1];
         }
       }
     }
@@ -239,7 +248,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int p = 0; p < NA; ++p) a[p][i] = As[buf][p][krow][wm0 + i * 16 + fr];
+        for (int p = 0; p < NA; ++p) a[p][i] = As[buf][p][a_at(wm0 + i * 16 + fr, krow)];
 #pragma unroll
       for (int j = 0; j < NI; ++j)
 #pragma unroll
