@@ -59,12 +59,12 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 //   B (4x16):  lane l holds B[l / 16][l % 16]
 //   D (16x16): lane l, element v holds D[l / 16 + 4 v][l % 16]
 // (the D layout was checked on gfx950 with a one-wave probe).
-// LDS keeps the B tile as stored (Bs[k][j]), so a fragment read is 16
-// consecutive doubles per k row.  The A tile is kept row-major with rows of
-// BK + 1 doubles (As[i][k]): its rows are written as loaded, without the
-// bank conflicts of a transposing write, and the 16 rows of a fragment read
-// fall on 16 distinct bank pairs.  A stored transposed (op T, H) arrives
-// k-major and is kept so (As[k][i], rows of BM + PAD).
+// LDS keeps each tile in its stored orientation.  Tiles stored k-major (B,
+// and A for op T / H) keep rows of BM (BN) + PAD doubles, so a fragment
+// read is 16 consecutive doubles per k row.  Tiles stored with contiguous k
+// (A, and B for op T / H) keep rows of BK + 1 doubles: their rows are
+// written as loaded, without the bank conflicts of a transposing write, and
+// the 16 rows of a fragment read fall on 16 distinct bank pairs.
 // ---------------------------------------------------------------------------
 // LDS of one FP64 GEMM tile (double-buffered A and B tiles).
 template <int KIND, int BM, int BN, int BK>
@@ -74,9 +74,11 @@ struct TileSmem {
   static constexpr int NB = (KIND == KIND_GAUSS || KIND == KIND_RC) ? 2 : 1;
   static constexpr int A_KM = BK * (BM + PAD), A_MM = BM * (BK + 1);
   static constexpr int A_SIZE = A_KM > A_MM ? A_KM : A_MM;
-  static_assert(A_SIZE % 2 == 0, "buffers stay 16-byte aligned");
+  static constexpr int B_KM = BK * (BN + PAD), B_NM = BN * (BK + 1);
+  static constexpr int B_SIZE = B_KM > B_NM ? B_KM : B_NM;
+  static_assert(A_SIZE % 2 == 0 && B_SIZE % 2 == 0, "buffers stay 16-byte aligned");
   __attribute__((aligned(16))) double As[2][NA][A_SIZE];
-  __attribute__((aligned(16))) double Bs[2][NB][BK][BN + PAD];
+  __attribute__((aligned(16))) double Bs[2][NB][B_SIZE];
 };
 
 // Stored operand tile: R rows of C contiguous elements (C even), moved in
@@ -132,11 +134,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   static_assert(BK % 4 == 0 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
   static_assert(((BN + PAD) * 8) % 16 == 0 && ((BM + PAD) * 8) % 16 == 0, "LDS rows must stay 16-byte aligned");
 
-  // Double-buffered LDS: A row-major with rows of BK + 1 (TA: k-major with
-  // rows of BM + PAD), B k-major.
+  // Double-buffered LDS in the stored orientations (see TileSmem).
   auto& As = sm.As;
   auto& Bs = sm.Bs;
   auto a_at = [](int i, int k) { return TA ? k * (BM + PAD) + i : i * (BK + 1) + k; };
+  auto b_at = [](int k, int j) { return TB ? j * (BK + 1) + k : k * (BN + PAD) + j; };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -214,10 +216,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
       for (int p = 0; p < NB; ++p) {
         if constexpr (TB) {
-          Bs[buf][p][c][r] = rb[p][2 * i];
-          Bs[buf][p][c + 1][r] = rb[p][2 * i + 1];
+          Bs[buf][p][b_at(c, r)] = rb[p][2 * i];
+          Bs[buf][p][b_at(c, r) + 1] = rb[p][2 * i + 1];
         } else {
-          *reinterpret_cast<d2*>(&Bs[buf][p][r][c]) = d2{rb[p][2 * i], rb[p][2 * i + 1]};
+          *reinterpret_cast<d2*>(&Bs[buf][p][b_at(r, c)]) = d2{rb[p][2 * i], rb[p][2 * i + 1]};
         }
       }
     }
@@ -252,7 +254,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
       for (int j = 0; j < NI; ++j)
 #pragma unroll
-        for (int p = 0; p < NB; ++p) b[p][j] = Bs[buf][p][krow][wn0 + j * 16 + fr];
+        for (int p = 0; p < NB; ++p) b[p][j] = Bs[buf][p][b_at(krow, wn0 + j * 16 + fr)];
       if constexpr (KIND == KIND_GAUSS) {
         double as[MI], bs[NI];
 #pragma unroll
