@@ -112,7 +112,10 @@ __device__ __forceinline__ void load_pairs(double (&dst)[2 * PAIRS], const doubl
 // epilogue.  Every thread of the block must call it (it synchronises).
 // TA / TB: the left / right operand is stored transposed (op T or H: the
 // left one k x m, the right one n x k).
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0>
+// DEEP: two register sets, global loads two k-steps ahead and the LDS store
+// of the next stage in the middle of the current k-step's MFMAs (32 more
+// registers; used where they fit without spills).
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0, int DEEP = 0>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
                                           TileSmem<KIND, BM, BN, BK>& sm) {
   constexpr int NWN = BN / WN;
@@ -160,10 +163,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   const bool interior = mrem >= BM && nrem >= BN;
   const bool fast = g.vec && interior;
 
-  double ra[NA][2 * A_PAIRS];
-  double rb[NB][2 * B_PAIRS];
+  // Register sets for the global tiles (DEEP: k-step j goes through set j % 2).
+  double ra0[NA][2 * A_PAIRS], ra1[NA][2 * A_PAIRS];
+  double rb0[NB][2 * B_PAIRS], rb1[NB][2 * B_PAIRS];
 
-  auto gload = [&](int64_t k0) {
+  auto gload = [&](int64_t k0, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
     const bool kfull = (k0 + BK <= g.k);
     const int64_t kleft = g.k - k0;
     // Stored tiles: A is BM x BK (TA: BK x BM) from k0, B is BK x BN (TB: BN x BK).
@@ -194,7 +198,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   };
   // A stored m-major (N) is transposed on the way into LDS; stored k-major
   // (TA) it goes in as is.  B the other way round.
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const double (&ra)[NA][2 * A_PAIRS], const double (&rb)[NB][2 * B_PAIRS]) {
 #pragma unroll
     for (int i = 0; i < A_PAIRS; ++i) {
       const int v = tid + i * NT;
@@ -235,55 +239,92 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 
   const double sL = g.sL, sR = g.sR;
   const int64_t nk = (g.k + BK - 1) / BK;
-  if (nk > 0) {
-    gload(0);
-    lstore(0);
-  }
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = (int)(kt & 1);
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+
+  // MFMAs of k-substeps [kk0, kk1) of the stage in LDS buffer buf.
+  auto compute = [&](int buf, int kk0, int kk1) {
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int krow = kk * 4 + fk;
-      double a[NA][MI], b[NB][NI];
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int p = 0; p < NA; ++p) a[p][i] = As[buf][p][a_at(wm0 + i * 16 + fr, krow)];
-#pragma unroll
-      for (int j = 0; j < NI; ++j)
-#pragma unroll
-        for (int p = 0; p < NB; ++p) b[p][j] = Bs[buf][p][b_at(krow, wn0 + j * 16 + fr)];
-      if constexpr (KIND == KIND_GAUSS) {
-        double as[MI], bs[NI];
-#pragma unroll
-        for (int i = 0; i < MI; ++i) as[i] = __builtin_fma(sL, a[NA - 1][i], a[0][i]);
-#pragma unroll
-        for (int j = 0; j < NI; ++j) bs[j] = __builtin_fma(sR, b[NB - 1][j], b[0][j]);
+      for (int kk = kk0; kk < kk1; ++kk) {
+        const int krow = kk * 4 + fk;
+        double a[NA][MI], b[NB][NI];
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < NI; ++j) {
-            acc[0][i][j] = mfma_f64(a[0][i], b[0][j], acc[0][i][j]);
-            acc[1 % NACC][i][j] = mfma_f64(a[NA - 1][i], b[NB - 1][j], acc[1 % NACC][i][j]);
-            acc[2 % NACC][i][j] = mfma_f64(as[i], bs[j], acc[2 % NACC][i][j]);
-          }
-      } else {
+          for (int p = 0; p < NA; ++p) a[p][i] = As[buf][p][a_at(wm0 + i * 16 + fr, krow)];
 #pragma unroll
-        for (int i = 0; i < MI; ++i)
+        for (int j = 0; j < NI; ++j)
 #pragma unroll
-          for (int j = 0; j < NI; ++j) {
-            acc[0][i][j] = mfma_f64(a[0][i], b[0][j], acc[0][i][j]);
-            if constexpr (KIND == KIND_RC)
-              acc[1 % NACC][i][j] = mfma_f64(a[0][i], b[NB - 1][j], acc[1 % NACC][i][j]);
-            if constexpr (KIND == KIND_CR)
-              acc[1 % NACC][i][j] = mfma_f64(a[NA - 1][i], b[0][j], acc[1 % NACC][i][j]);
-          }
+          for (int p = 0; p < NB; ++p) b[p][j] = Bs[buf][p][b_at(krow, wn0 + j * 16 + fr)];
+        if constexpr (KIND == KIND_GAUSS) {
+          double as[MI], bs[NI];
+#pragma unroll
+          for (int i = 0; i < MI; ++i) as[i] = __builtin_fma(sL, a[NA - 1][i], a[0][i]);
+#pragma unroll
+          for (int j = 0; j < NI; ++j) bs[j] = __builtin_fma(sR, b[NB - 1][j], b[0][j]);
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+              acc[0][i][j] = mfma_f64(a[0][i], b[0][j], acc[0][i][j]);
+              acc[1 % NACC][i][j] = mfma_f64(a[NA - 1][i], b[NB - 1][j], acc[1 % NACC][i][j]);
+              acc[2 % NACC][i][j] = mfma_f64(as[i], bs[j], acc[2 % NACC][i][j]);
+            }
+        } else {
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+              acc[0][i][j] = mfma_f64(a[0][i], b[0][j], acc[0][i][j]);
+              if constexpr (KIND == KIND_RC)
+                acc[1 % NACC][i][j] = mfma_f64(a[0][i], b[NB - 1][j], acc[1 % NACC][i][j]);
+              if constexpr (KIND == KIND_CR)
+                acc[1 % NACC][i][j] = mfma_f64(a[NA - 1][i], b[0][j], acc[1 % NACC][i][j]);
+            }
+        }
       }
+  };
+
+  if constexpr (!DEEP) {
+    if (nk > 0) {
+      gload(0, ra0, rb0);
+      lstore(0, ra0, rb0);
     }
-    if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int buf = (int)(kt & 1);
+      if (kt + 1 < nk) gload((kt + 1) * BK, ra0, rb0);
+      compute(buf, 0, BK / 4);
+      if (kt + 1 < nk) lstore(buf ^ 1, ra0, rb0);
+      __syncthreads();
+    }
+  } else {
+    // k-step kt on LDS buffer kt % 2: the loads of k-step kt + 2 go into the
+    // free set (rl); half-way through the MFMAs the tiles of k-step kt + 1
+    // (set rs, loaded a k-step ago) go into the other buffer, which every
+    // wave finished reading before the last barrier.  The barrier waits for
+    // the LDS writes only, so the loads of k-step kt + 2 stay in flight.
+    auto step = [&](int64_t kt, double (&ral)[NA][2 * A_PAIRS], double (&rbl)[NB][2 * B_PAIRS],
+                    const double (&ras)[NA][2 * A_PAIRS], const double (&rbs)[NB][2 * B_PAIRS]) {
+      const int buf = (int)(kt & 1);
+      if (kt + 2 < nk) gload((kt + 2) * BK, ral, rbl);
+      compute(buf, 0, BK / 8);
+      if (kt + 1 < nk) lstore(buf ^ 1, ras, rbs);
+      compute(buf, BK / 8, BK / 4);
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS writes are done
+      __builtin_amdgcn_s_barrier();
+    };
+    if (nk > 0) {
+      gload(0, ra0, rb0);
+      lstore(0, ra0, rb0);
+      if (nk > 1) gload(BK, ra1, rb1);
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    int64_t kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+      step(kt, ra0, rb0, ra1, rb1);
+      step(kt + 1, ra1, rb1, ra0, rb0);
+    }
+    if (kt < nk) step(kt, ra0, rb0, ra1, rb1);
   }
 
   // Epilogue: P from the accumulators, then coef * P into each target.
@@ -332,7 +373,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
       }
 }
 
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0>
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0, int DEEP = 0>
 __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 cgemm_f64(const GemmArgs g) {
@@ -341,7 +382,7 @@ cgemm_f64(const GemmArgs g) {
   const int tiles_n = (int)((g.n + BN - 1) / BN);
   int tm, tn;
   tile_coords(tiles_m, tiles_n, g.xcd_remap, g.group_m, tm, tn);
-  gemm_tile<KIND, BM, BN, BK, WM, WN, TA, TB>(g, (int64_t)tm * BM, (int64_t)tn * BN, sm);
+  gemm_tile<KIND, BM, BN, BK, WM, WN, TA, TB, DEEP>(g, (int64_t)tm * BM, (int64_t)tn * BN, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -532,14 +573,14 @@ int default_tile_config(int kind, int64_t m, int64_t n, int64_t k) {
   return 0;
 }
 
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0>
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0, int DEEP = 0>
 static hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
   const int64_t tm = (g.m + BM - 1) / BM, tn = (g.n + BN - 1) / BN;
   const int64_t tiles = tm * tn;
   if (tiles <= 0) return hipSuccess;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   constexpr int NT = (BM / WM) * (BN / WN) * 64;
-  hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE, TA, TB>), dim3((unsigned)tiles), dim3(NT), 0, s, g);
+  hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE, TA, TB, DEEP>), dim3((unsigned)tiles), dim3(NT), 0, s, g);
   return hipGetLastError();
 }
 
@@ -552,7 +593,14 @@ static hipError_t launch_kind(const GemmArgs& g, int cfg, hipStream_t s) {
     return launch_one<KIND, 64, 64, 16, 32, 32, 2, 0, 1>(g, s);
   }
   switch (cfg) {
-    case 0: return launch_one<KIND, 64, 64, 16, 32, 32, 2>(g, s);
+    case 0:
+      // Large complex products take the two-deep pipeline (1 % faster at
+      // n = 16384); short k loops and small grids do better without it.
+      if constexpr (KIND == KIND_GAUSS) {
+        const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
+        if (g.k >= 1024 && tiles >= 1024) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 0, 0, 1>(g, s);
+      }
+      return launch_one<KIND, 64, 64, 16, 32, 32, 2>(g, s);
     case 1: return launch_one<KIND, 64, 64, 16, 32, 32, 1>(g, s);
     case 2: return launch_one<KIND, 128, 64, 16, 64, 32, 1>(g, s);
     case 3: return launch_one<KIND, 64, 64, 32, 32, 32, 2>(g, s);
