@@ -111,6 +111,17 @@ class SmiSampler:
 
         self.exe = shutil.which("amd-smi") or ("/opt/rocm/bin/amd-smi" if os.path.exists("/opt/rocm/bin/amd-smi")
                                                else None)
+        # Under a profiler every child process starts with the profiler's
+        # library, which initialises the GPU: no child processes then.
+        if any(k.startswith("ROCPROF") for k in os.environ):
+            self.exe = None
+        self.cmd = None
+        if self.exe:
+            # A Python script is run by this interpreter, not through its
+            # "#!/usr/bin/env" line (one program start, no exec hop).
+            with open(self.exe, "rb") as f:
+                first = f.readline()
+            self.cmd = [sys.executable, self.exe] if first.startswith(b"#!") and b"python" in first else [self.exe]
         self.interval = interval
         self.samples = []
         self._stop = threading.Event()
@@ -119,7 +130,7 @@ class SmiSampler:
     def _one(self):
         import subprocess
 
-        out = subprocess.run([self.exe, "metric", "-p", "-c", "--json"], capture_output=True, text=True,
+        out = subprocess.run(self.cmd + ["metric", "-p", "-c", "--json"], capture_output=True, text=True,
                              timeout=10).stdout
         g = json.loads(out)["gpu_data"][0]
         clocks = [v["clk"]["value"] for k, v in g["clock"].items()
