@@ -332,3 +332,24 @@ def test_large_gaussian_probe(bq):
     rho = oracle.rel_frobenius(CX, ABX)
     print(f"n={n}: Gaussian-probe relative error estimate {rho:.3e}", flush=True)
     assert rho <= TOL
+
+
+@pytest.mark.parametrize("k", [1040, 1031, 1024])
+def test_large_products_odd_and_ragged_k(bq, k):
+    """m = n = 2048 (1024 tiles) with k >= 1024 takes the two-deep pipeline:
+    an odd k-step count (k = 1040: 65 steps), a ragged last k-step (1031)
+    and an even count (1024), checked against the oracle on sampled rows and
+    columns (the last ones included)."""
+    import torch
+
+    m = n = 2048
+    rng = np.random.default_rng(70 + k)
+    A = torch.from_numpy(inputs.blocks(rng, m, k, "uniform")).to("cuda")
+    B = torch.from_numpy(inputs.blocks(rng, k, n, "uniform")).to("cuda")
+    C = bq.bq_gemm(A, B)
+    torch.cuda.synchronize()
+    rows, cols = _sample(m, 40, 71), _sample(n, 40, 72)
+    ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+    got = C[:, ri][:, :, ci].cpu().numpy()
+    ref = oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy())
+    assert oracle.rel_frobenius(got, ref) <= TOL
