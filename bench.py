@@ -316,7 +316,60 @@ def ops_leg(bq, inputs, torch, n, log):
     return out
 
 
-def batched_leg(bq, inputs, torch, count, log):
+def subalg_leg(bq, inputs, torch, n, log):
+    """The four subalgebras of one n x n product (N(0,1) entries, seed 2):
+    biquaternion, real quaternion (units 1, i, j, k), complex (the field
+    spanned by 1 and the commuting imaginary unit) and real, each through
+    bq_gemm with its component mask and through its own entry point; per
+    case the median of 5 timed calls.  Effective rates count the
+    component-wise form of each algebra (64 / 16 / 4 / 1 real GEMMs)."""
+    import numpy as np
+
+    rng = np.random.default_rng(2)
+    A = torch.from_numpy(inputs.blocks(rng, n, n, "normal")).to("cuda")
+    B = torch.from_numpy(inputs.blocks(rng, n, n, "normal")).to("cuda")
+    C = torch.empty_like(A)
+    res, _ = bq.workspace_size(n, n, n)
+    ws = torch.empty(res, dtype=torch.uint8, device="cuda")
+
+    def median_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[reps // 2]
+
+    cases = [("biquaternion", bq.FULL, 64, None),
+             ("real_quaternion", bq.REAL_QUAT, 16,
+              lambda: bq.rq_gemm([A[u] for u in range(4)], [B[u] for u in range(4)], [C[u] for u in range(4)],
+                                 workspace=ws)),
+             ("complex", bq.COMPLEX, 4, lambda: bq.cx_gemm((A[0], A[4]), (B[0], B[4]), (C[0], C[4]))),
+             ("real", bq.REAL, 1, lambda: bq.re_gemm(A[0], B[0], C[0]))]
+    out = {"workload": f"N(0,1) n={n} (seed 2), FP64, one product per subalgebra"}
+    for name, mask, eff_gemms, variant in cases:
+        ms = median_ms(lambda: bq.bq_gemm(A, B, C, mask_a=mask, mask_b=mask, workspace=ws))
+        gemms = bq.plan_real_gemms(mask, mask)
+        exec_tf = gemms * 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        d = {"real_gemms": gemms, "ms": round(ms, 3),
+             "eff_tflops": round(eff_gemms * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2),
+             "exec_tflops": round(exec_tf, 2), "exec_frac_of_fp64_peak": round(exec_tf / PEAK_FP64_TFLOPS, 4)}
+        if variant is not None:
+            d["own_entry_point_ms"] = round(median_ms(variant), 3)
+        out[name] = d
+        log(f"subalgebra {name}: {gemms} real GEMMs, {ms:.2f} ms, {exec_tf:.1f} TFLOP/s executed")
+    del A, B, C, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_leg(bq, inputs, torch, count, log, split_prec=None):
     """count products, square sizes log-uniform over 64..1536 (seed 5),
     uniform[-1, 1]: one grouped plan (graph of a pre-combination launch and
     a persistent launch, autotuned) against a loop of single calls."""
@@ -357,11 +410,41 @@ def batched_leg(bq, inputs, torch, count, log):
             bq.bq_gemm(A, B, C, workspace=ws)
     l_ms = timed(loop, 2)
     log(f"batched: grouped {g_ms:.1f} ms, loop {l_ms:.1f} ms")
-    return {"workload": f"{count} products, n log-uniform over 64..1536 (seed 5), uniform[-1,1], FP64",
-            "grouped_ms": round(g_ms, 2), "grouped_eff_tflops": round(flop_eff / (g_ms * 1e-3) / 1e12, 2),
-            "grouped_exec_tflops": round(flop_exec / (g_ms * 1e-3) / 1e12, 2),
-            "loop_ms": round(l_ms, 2), "loop_eff_tflops": round(flop_eff / (l_ms * 1e-3) / 1e12, 2),
-            "speedup_vs_loop": round(l_ms / g_ms, 3), "plan": info, "plan_create_and_autotune_s": round(tune_s, 2)}
+    out = {"workload": f"{count} products, n log-uniform over 64..1536 (seed 5), uniform[-1,1], FP64",
+           "grouped_ms": round(g_ms, 2), "grouped_eff_tflops": round(flop_eff / (g_ms * 1e-3) / 1e12, 2),
+           "grouped_exec_tflops": round(flop_exec / (g_ms * 1e-3) / 1e12, 2),
+           "loop_ms": round(l_ms, 2), "loop_eff_tflops": round(flop_eff / (l_ms * 1e-3) / 1e12, 2),
+           "speedup_vs_loop": round(l_ms / g_ms, 3), "plan": info, "plan_create_and_autotune_s": round(tune_s, 2)}
+    del ws
+    if split_prec:
+        # The same batch in a split form, one graph.  Three products (the
+        # largest and two drawn by seed) go back to the host with both
+        # results; the CPU baseline leg scores them against the oracle.
+        import numpy as np
+
+        check = [int(np.argmax(sizes))] + [int(i) for i in np.random.default_rng(6).choice(len(sizes), 2, replace=False)]
+        fp64_c = {i: probs[i][2].cpu().numpy() for i in check}
+        sprobs = [(A, B, torch.empty_like(C)) for (A, B, C) in probs]
+        t0 = time.time()
+        splan = bq.GroupedPlan(sprobs, prec=split_prec)
+        splan.autotune()
+        stune_s = time.time() - t0
+        s_ms = timed(splan.launch, 3)
+        splan.close()
+        host = [(probs[i][0].cpu().numpy(), probs[i][1].cpu().numpy(), fp64_c[i], sprobs[i][2].cpu().numpy())
+                for i in check]
+        out["split"] = {"prec": split_prec, "grouped_ms": round(s_ms, 2),
+                        "grouped_eff_tflops": round(flop_eff / (s_ms * 1e-3) / 1e12, 2),
+                        "speed_vs_fp64_grouped": round(g_ms / s_ms, 3),
+                        "plan_create_and_autotune_s": round(stune_s, 2),
+                        "checked_sizes": [sizes[i] for i in check],
+                        "max_rel_err_vs_oracle": None, "fp64_max_rel_err_vs_oracle": None}
+        log(f"batched {split_prec}: grouped {s_ms:.1f} ms")
+        del sprobs
+        out["_host_checks"] = host
+    del probs
+    torch.cuda.empty_cache()
+    return out
 
 
 def sample_idx(n, r, seed):
@@ -390,6 +473,10 @@ def main():
     ap.add_argument("--paper-n", type=int, default=0,
                     help="optional: time one product of this n with host-resident inputs and output, "
                          "transfers included, as the paper times its GPU runs (0 = skip)")
+    ap.add_argument("--subalg-n", type=int, default=4096,
+                    help="size of the subalgebra leg (0 skips it)")
+    ap.add_argument("--batched-split", default="split_int8_crt",
+                    help="split form the batch is repeated in (empty skips it)")
     ap.add_argument("--batched", type=int, default=512,
                     help="products in the batched leg (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -607,40 +694,23 @@ def main():
                     samples["split_int8_crt_at_5e-13"] = cn
     bq.trace_enable(False)
 
-    # CPU baseline leg: the oracle, timed on the sampled sub-block with the
-    # full k, on the host's cores; it also scores every sampled result.
-    cpu = None
-    rel_err = None
-    if r > 0:
-        import oracle
-
-        As = A[:, ri, :].cpu().numpy()
-        Bs = B[:, :, ci].cpu().numpy()
-        log(f"oracle on a {r}x{r} sampled sub-block (k = {n}) with {oracle.num_threads()} threads")
-        t0 = time.perf_counter()
-        ref = oracle.gemm(As, Bs)
-        t_cpu = time.perf_counter() - t0
-        rel_err = oracle.rel_frobenius(samples["fp64"], ref)
-        for prec in split:
-            split[prec]["rel_err_sampled_vs_oracle"] = oracle.rel_frobenius(samples[prec], ref)
-        cpu = {"value": round(64 * 2.0 * r * r * n / t_cpu / 1e12, 6),
-               "unit": "effective TFLOP/s (64 real GEMMs counted)", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"C[R,S] for {r} sampled rows R and {r} columns S (last row/column included) "
-                         f"of the n={n} product, full k={n}: {t_cpu:.2f} s",
-               "seconds": round(t_cpu, 3)}
-        log(f"oracle {t_cpu:.1f}s, sampled rel Frobenius error {rel_err:.3e}")
+    # Host copies of the sampled operands for the CPU baseline leg.
+    As = A[:, ri, :].cpu().numpy() if r > 0 else None
+    Bs = B[:, :, ci].cpu().numpy() if r > 0 else None
 
     batched = None
     heev = None
     ops = None
-    if args.batched > 0 or args.heev > 0 or args.ops_n > 0 or args.paper_n > 0:
+    subalg = None
+    if args.batched > 0 or args.heev > 0 or args.ops_n > 0 or args.paper_n > 0 or args.subalg_n > 0:
         del A, B, C
         torch.cuda.empty_cache()
     if args.ops_n > 0:
         ops = ops_leg(bq, inputs, torch, args.ops_n, log)
+    if args.subalg_n > 0:
+        subalg = subalg_leg(bq, inputs, torch, args.subalg_n, log)
     if args.batched > 0:
-        batched = batched_leg(bq, inputs, torch, args.batched, log)
+        batched = batched_leg(bq, inputs, torch, args.batched, log, args.batched_split)
     if args.heev > 0:
         bq.trace_enable(True)
         heev = heev_leg(bq, inputs, torch, args.heev, log)
@@ -648,6 +718,40 @@ def main():
     paper_like = None
     if args.paper_n > 0:
         paper_like = paper_like_leg(bq, inputs, torch, args.paper_n, log)
+
+    # CPU baseline leg: the oracle, timed on the sampled sub-block with the
+    # full k on the host's cores; it also scores every sampled result and
+    # the batch's checked products.
+    cpu = None
+    rel_err = None
+    host_checks = batched.pop("_host_checks", None) if batched else None
+    if r > 0 or host_checks:
+        import oracle
+
+        if r > 0:
+            log(f"oracle on a {r}x{r} sampled sub-block (k = {n}) with {oracle.num_threads()} threads")
+            t0 = time.perf_counter()
+            ref = oracle.gemm(As, Bs)
+            t_cpu = time.perf_counter() - t0
+            rel_err = oracle.rel_frobenius(samples["fp64"], ref)
+            for prec in split:
+                split[prec]["rel_err_sampled_vs_oracle"] = oracle.rel_frobenius(samples[prec], ref)
+            cpu = {"value": round(64 * 2.0 * r * r * n / t_cpu / 1e12, 6),
+                   "unit": "effective TFLOP/s (64 real GEMMs counted)", "cores": oracle.num_threads(),
+                   "kind": "oracle",
+                   "sample": f"C[R,S] for {r} sampled rows R and {r} columns S (last row/column included) "
+                             f"of the n={n} product, full k={n}: {t_cpu:.2f} s",
+                   "seconds": round(t_cpu, 3)}
+            log(f"oracle {t_cpu:.1f}s, sampled rel Frobenius error {rel_err:.3e}")
+        if host_checks:
+            ef, es = [], []
+            for (Ah, Bh, Cf, Cs) in host_checks:
+                ref = oracle.gemm(Ah, Bh)
+                ef.append(oracle.rel_frobenius(Cf, ref))
+                es.append(oracle.rel_frobenius(Cs, ref))
+            batched["split"]["max_rel_err_vs_oracle"] = max(es)
+            batched["split"]["fp64_max_rel_err_vs_oracle"] = max(ef)
+            log(f"batched checks vs oracle: split {max(es):.2e}, fp64 {max(ef):.2e}")
 
     out = {"metric": METRIC, "value": round(eff_tflops, 3), "unit": "effective TFLOP/s (64 real GEMMs counted)",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -662,7 +766,7 @@ def main():
            "mfma_frac_of_fp64_peak": round(exec_tflops / PEAK_FP64_TFLOPS, 4),
            "rel_err_sampled_vs_oracle": rel_err,
            "roofline": roofline, "combine": combine, "cpu_baseline": cpu,
-           "split_precision": split, "op_pairs": ops, "batched": batched, "diagonalization": heev,
+           "split_precision": split, "op_pairs": ops, "subalgebras": subalg, "batched": batched, "diagonalization": heev,
            "slab_one_of_8": slab, "paper_like": paper_like}
     print(json.dumps(out), flush=True)
 

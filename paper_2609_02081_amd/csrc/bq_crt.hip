@@ -79,9 +79,8 @@ __device__ __forceinline__ void crt_residues(double x, int e, int b, signed char
 // writes 128 contiguous bytes of each plane.  grid.x = rows_pad,
 // grid.y = kp / 512.
 template <int N>
-__global__ void __launch_bounds__(256) crt_split_left(const SplitArgs a, const int* exps, void* out) {
-  const int64_t r = blockIdx.x;
-  const int64_t kk = (int64_t)blockIdx.y * 512 + threadIdx.x * 2;
+__device__ __forceinline__ void crt_split_left_at(const SplitArgs& a, const int* exps, void* out, int64_t r,
+                                                  int64_t kk) {
   if (kk >= a.kp) return;
   const int e = (r < a.rows) ? exps[r] : INT_MIN;
   signed char q[2][N];
@@ -98,14 +97,20 @@ __global__ void __launch_bounds__(256) crt_split_left(const SplitArgs a, const i
         (unsigned short)((unsigned char)q[0][i] | ((unsigned)(unsigned char)q[1][i] << 8));
 }
 
+template <int N>
+__global__ void __launch_bounds__(256) crt_split_left(const SplitArgs a, const int* exps, void* out) {
+  crt_split_left_at<N>(a, exps, out, blockIdx.x, (int64_t)blockIdx.y * 512 + threadIdx.x * 2);
+}
+
 // Right factor (k x n): residues stored transposed, R[i][col][kk].  Thread:
 // one column and 16 consecutive kk (one 16-byte chunk of each plane),
 // consecutive lanes on consecutive columns, so every row read is coalesced
 // and no LDS transpose is needed.  grid.x = cols_pad / 64, grid.y = kp / 64.
 template <int N>
-__global__ void __launch_bounds__(256) crt_split_right(const SplitArgs a, const int* exps, void* out) {
-  const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int64_t k0 = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+__device__ __forceinline__ void crt_split_right_block(const SplitArgs& a, const int* exps, void* out, int64_t bx,
+                                                      int64_t by) {
+  const int64_t c = bx * 64 + (threadIdx.x & 63);
+  const int64_t k0 = by * 64 + (threadIdx.x >> 6) * 16;
   const int e = (c < a.cols) ? exps[c] : INT_MIN;
   i4v q[N];
 #pragma unroll
@@ -125,25 +130,53 @@ __global__ void __launch_bounds__(256) crt_split_right(const SplitArgs a, const 
     *reinterpret_cast<i4v*>(static_cast<unsigned char*>(out) + (int64_t)i * a.slice_stride + o) = q[i];
 }
 
+template <int N>
+__global__ void __launch_bounds__(256) crt_split_right(const SplitArgs a, const int* exps, void* out) {
+  crt_split_right_block<N>(a, exps, out, blockIdx.x, blockIdx.y);
+}
+
+// Exponents of one operand without atomics (grouped launches): a row-kernel
+// operand takes one block per row, a column-kernel operand one block per 64
+// columns over all its rows; every block writes its exponents once.
+__device__ __forceinline__ void crt_exp_block(const SplitArgs& a, int* exps, int64_t b, int* red) {
+  int e = INT_MIN;
+  if (a.left) {
+    const int64_t r = b;
+    for (int64_t c = threadIdx.x; c < a.cols; c += 256) e = max(e, exp_of(operand_value(a, r * a.ld + c)));
+    for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      e = max(max(red[0], red[1]), max(red[2], red[3]));
+      exps[r] = exp_special(e) ? e : e + a.head;
+    }
+  } else {
+    const int64_t c = b * 64 + (threadIdx.x & 63);
+    if (c < a.cols)
+      for (int64_t r = threadIdx.x >> 6; r < a.rows; r += 4) e = max(e, exp_of(operand_value(a, r * a.ld + c)));
+    red[threadIdx.x] = e;
+    __syncthreads();
+    if (threadIdx.x < 64 && c < a.cols) {
+      e = max(max(red[threadIdx.x], red[threadIdx.x + 64]), max(red[threadIdx.x + 128], red[threadIdx.x + 192]));
+      exps[c] = exp_special(e) ? e : e + a.head;
+    }
+  }
+}
+
 // One INT8 GEMM per modulus (blockIdx.y): residue planes of X (rows padded
 // to 256) and Y (columns padded to 256) in the tiled 64-byte layout, a 128 x
 // 128 block of 4 waves (64 x 64 each, 16 v_mfma_i32_16x16x64_i8 per k-step),
 // four LDS stages filled straight from global memory three k-steps ahead,
 // every wave moving 4 of the stage's 16 KB.  The int32 result is reduced to
 // its symmetric residue and stored as a byte plane R[i][row][col].
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-crt_gemm(const CrtGemmArgs g) {
+constexpr int kCrtGemmLds = 4 * 4 * 64 * 64;  // four stages of two A and two B 4 KB tiles
+
+__device__ __forceinline__ void crt_gemm_block(const CrtGemmArgs& g, int tm, int tn, int mod, unsigned char* lds) {
   constexpr int BM = 128, BN = 128, ROWB = 64, TILE = 64 * ROWB;  // 4 KB per 64-row tile
   constexpr int STAGE = 4 * TILE;                                  // two A tiles, two B tiles
   constexpr int NST = 4, NPW = 4;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[NST * STAGE];
-  const int mod = blockIdx.y;
+  static_assert(NST * STAGE == kCrtGemmLds, "LDS size");
   const int p = kCrtModuli[mod];
-
-  const int tiles_m = (int)((g.m + BM - 1) / BM);
-  const int tiles_n = (int)((g.n + BN - 1) / BN);
-  int tm, tn;
-  slice_tile_coords(tiles_m, tiles_n, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -204,19 +237,40 @@ crt_gemm(const CrtGemmArgs g) {
     block_sync();
   }
   wait_vm<0>();
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  block_sync();
 
-  signed char* out = g.out + (int64_t)mod * g.plane_r;
+  // Residues into a 128 x 128 byte tile in LDS (rows of OUT_LD bytes), then
+  // 16-byte row stores (columns up to ldr, a multiple of 16).
+  constexpr int OUT_LD = BN + 16;
+  static_assert(BM * OUT_LD <= kCrtGemmLds, "output tile fits the stages");
   const double pd = (double)p, inv_p = 1.0 / pd;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = m0 + wm0 + i * 16 + 4 * fg + v;
-        const int64_t c = n0 + wn0 + j * 16 + fr;
-        if (r < g.m && c < g.n) out[r * g.ldr + c] = (signed char)sym_mod_rt(acc[i][j][v], pd, inv_p);
-      }
+      for (int v = 0; v < 4; ++v)
+        lds[(wm0 + i * 16 + 4 * fg + v) * OUT_LD + wn0 + j * 16 + fr] =
+            (unsigned char)sym_mod_rt(acc[i][j][v], pd, inv_p);
+  __syncthreads();
+  signed char* out = g.out + (int64_t)mod * g.plane_r;
+  for (int w = tid; w < BM * (BN / 16); w += 256) {
+    const int r = w / (BN / 16), ch = w % (BN / 16);
+    const int64_t grow = m0 + r, gcol = n0 + ch * 16;
+    if (grow < g.m && gcol < g.ldr)
+      *reinterpret_cast<i4v*>(out + grow * g.ldr + gcol) = *reinterpret_cast<const i4v*>(lds + r * OUT_LD + ch * 16);
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+crt_gemm(const CrtGemmArgs g) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kCrtGemmLds];
+  const int tiles_m = (int)((g.m + 127) / 128);
+  const int tiles_n = (int)((g.n + 127) / 128);
+  int tm, tn;
+  slice_tile_coords(tiles_m, tiles_n, tm, tn);
+  crt_gemm_block(g, tm, tn, blockIdx.y, lds);
 }
 
 // The same GEMM for large products: a 256 x 256 block of 4 waves (128 x 128
@@ -372,6 +426,7 @@ constexpr int kCombineCols = 4;
 struct CrtLds {
   double cpart[kMaxCrtModuli][4];
   double frac[kMaxCrtModuli];
+  double mpart[4];
 };
 
 template <int N>
@@ -399,7 +454,7 @@ __device__ __forceinline__ void crt_values(const CrtCombineArgs& g, const CrtLds
   }
   unsigned __int128 Mu = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) Mu |= (unsigned __int128)(uint32_t)g.mpart[j] << (32 * j);
+  for (int j = 0; j < 4; ++j) Mu |= (unsigned __int128)(uint32_t)K.mpart[j] << (32 * j);
   const __int128 M = (__int128)Mu;
   constexpr double two32 = 4294967296.0, inv32 = 1.0 / 4294967296.0;
 #pragma unroll
@@ -408,7 +463,7 @@ __device__ __forceinline__ void crt_values(const CrtCombineArgs& g, const CrtLds
     uint32_t limb[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      double y = __builtin_fma(-q, g.mpart[j], x[e][j]);
+      double y = __builtin_fma(-q, K.mpart[j], x[e][j]);
       const double f = floor(y * inv32);
       y = __builtin_fma(-f, two32, y);
       if (j < 3) x[e][j + 1] += f;
@@ -429,15 +484,20 @@ __device__ __forceinline__ void crt_values(const CrtCombineArgs& g, const CrtLds
   }
 }
 
+// Constants of the first N moduli into LDS (every thread calls it).
 template <int N>
-__global__ void __launch_bounds__(256) crt_combine(const CrtCombineArgs g) {
-  __shared__ CrtLds K;
-  for (int t = threadIdx.x; t < N * 4; t += 256) K.cpart[t / 4][t % 4] = g.cpart[t / 4][t % 4];
-  for (int t = threadIdx.x; t < N; t += 256) K.frac[t] = g.frac[t];
+__device__ __forceinline__ void crt_stage_consts(CrtLds& K, const double (&cpart)[kMaxCrtModuli][4],
+                                                 const double (&frac)[kMaxCrtModuli], const double (&mpart)[4]) {
+  for (int t = threadIdx.x; t < N * 4; t += 256) K.cpart[t / 4][t % 4] = cpart[t / 4][t % 4];
+  for (int t = threadIdx.x; t < N; t += 256) K.frac[t] = frac[t];
+  if (threadIdx.x < 4) K.mpart[threadIdx.x] = mpart[threadIdx.x];
   __syncthreads();
-  const int64_t bpr = (g.n + 256 * kCombineCols - 1) / (256 * kCombineCols);
-  const int64_t r = blockIdx.x / bpr;
-  const int64_t c0 = (blockIdx.x % bpr) * (256 * kCombineCols) + threadIdx.x * kCombineCols;
+}
+
+// Columns c0 .. c0 + kCombineCols - 1 of row r of the reconstruction of
+// one complex product.
+template <int N>
+__device__ __forceinline__ void crt_combine_at(const CrtCombineArgs& g, const CrtLds& K, int64_t r, int64_t c0) {
   if (r >= g.m || c0 >= g.n) return;
   double t[kCrtProducts][kCombineCols];
 #pragma unroll
@@ -477,6 +537,92 @@ __global__ void __launch_bounds__(256) crt_combine(const CrtCombineArgs g) {
   }
 }
 
+template <int N>
+__global__ void __launch_bounds__(256) crt_combine(const CrtCombineArgs g) {
+  __shared__ CrtLds K;
+  crt_stage_consts<N>(K, g.cpart, g.frac, g.mpart);
+  const int64_t bpr = (g.n + 256 * kCombineCols - 1) / (256 * kCombineCols);
+  crt_combine_at<N>(g, K, blockIdx.x / bpr, (blockIdx.x % bpr) * (256 * kCombineCols) + threadIdx.x * kCombineCols);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped forms: one launch over the items of many problems.
+// ---------------------------------------------------------------------------
+// The Chinese remainder constants of one modulus count (filled on the host).
+struct CrtConsts {
+  double cpart[kMaxCrtModuli][4];
+  double frac[kMaxCrtModuli];
+  double mpart[4];
+};
+
+// Last item whose first block is at or before block b.
+__device__ __forceinline__ int crt_find_item(const int64_t* prefix, int count, int64_t b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) crt_exp_grouped(const CrtSplitItem* items, const int64_t* prefix, int count) {
+  __shared__ int red[256];
+  const int64_t b = blockIdx.x;
+  const int i = crt_find_item(prefix, count, b);
+  crt_exp_block(items[i].a, items[i].exps, b - prefix[i], red);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) crt_split_grouped(const CrtSplitItem* items, const int64_t* prefix, int count) {
+  const int64_t b = blockIdx.x;
+  const int i = crt_find_item(prefix, count, b);
+  const CrtSplitItem& it = items[i];
+  const int64_t local = b - prefix[i];
+  if (it.a.left) {
+    // thread: one pair of kk of one row, pairs of consecutive rows packed
+    // into the block (padding rows are left alone: their GEMM rows are
+    // never stored)
+    const int64_t pairs = it.a.kp / 2;
+    const int64_t q = local * 256 + threadIdx.x;
+    const int64_t r = q / pairs;
+    if (r >= it.a.rows) return;
+    crt_split_left_at<N>(it.a, it.exps, it.out, r, (q % pairs) * 2);
+  } else {
+    const int64_t nky = it.a.kp / 64;
+    crt_split_right_block<N>(it.a, it.exps, it.out, local / nky, local % nky);
+  }
+}
+
+// Item blocks run modulus by modulus, tiles row by row within a modulus.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+crt_gemm_grouped(const CrtGemmItem* items, const int64_t* prefix, int count) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kCrtGemmLds];
+  const int64_t b = blockIdx.x;
+  const int i = crt_find_item(prefix, count, b);
+  const CrtGemmArgs& g = items[i].g;
+  const int tiles_n = (int)((g.n + 127) / 128);
+  const int64_t tiles = ((g.m + 127) / 128) * tiles_n;
+  const int64_t local = b - prefix[i];
+  const int t = (int)(local % tiles);
+  crt_gemm_block(g, t / tiles_n, t % tiles_n, (int)(local / tiles), lds);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) crt_combine_grouped(const CrtCombineArgs* items, const int64_t* prefix,
+                                                           int count, const CrtConsts k) {
+  __shared__ CrtLds K;
+  crt_stage_consts<N>(K, k.cpart, k.frac, k.mpart);
+  const int64_t b = blockIdx.x;
+  const int i = crt_find_item(prefix, count, b);
+  // thread: one group of kCombineCols columns; groups of consecutive rows
+  // packed into the block
+  const CrtCombineArgs& g = items[i];
+  const int64_t qpr = (g.n + kCombineCols - 1) / kCombineCols;
+  const int64_t q = (b - prefix[i]) * 256 + threadIdx.x;
+  crt_combine_at<N>(g, K, q / qpr, (q % qpr) * kCombineCols);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -495,11 +641,6 @@ static hipError_t launch_crt_split_n(const SplitArgs& a, int* exps, void* out, h
 // Chinese remainder constants of the first N moduli, exact (base-2^32
 // big integers): c_i = M_i (M_i^-1 mod p_i) with M_i = M / p_i and M, kept
 // modulo 2^128 as four 32-bit parts (exact in FP64), and c_i / M in FP64.
-struct CrtConsts {
-  double cpart[kMaxCrtModuli][4];
-  double frac[kMaxCrtModuli];
-  double mpart[4];
-};
 
 static std::vector<uint32_t> big_mul(std::vector<uint32_t> v, uint32_t x) {
   uint64_t carry = 0;
@@ -617,5 +758,62 @@ hipError_t launch_crt_combine(int N, const CrtCombineArgs& g, hipStream_t st) {
 }
 
 int crt_modulus(int i) { return (i >= 0 && i < kMaxCrtModuli) ? kCrtModuli[i] : 0; }
+
+int64_t crt_combine_blocks(const CrtCombineArgs& c) {
+  return (c.m * ((c.n + kCombineCols - 1) / kCombineCols) + 255) / 256;
+}
+
+hipError_t launch_crt_exp_grouped(const CrtSplitItem* items, const int64_t* prefix, int count, int64_t blocks,
+                                  hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(crt_exp_grouped, dim3((unsigned)blocks), dim3(256), 0, st, items, prefix, count);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_crt_split_grouped_n(const CrtSplitItem* items, const int64_t* prefix, int count,
+                                             int64_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL((crt_split_grouped<N>), dim3((unsigned)blocks), dim3(256), 0, st, items, prefix, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_crt_split_grouped(int N, const CrtSplitItem* items, const int64_t* prefix, int count,
+                                    int64_t blocks, hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+#define X(NN) \
+  if (N == NN) return launch_crt_split_grouped_n<NN>(items, prefix, count, blocks, st);
+  BQ_CRT_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_crt_gemm_grouped(const CrtGemmItem* items, const int64_t* prefix, int count, int64_t blocks,
+                                   hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(crt_gemm_grouped, dim3((unsigned)blocks), dim3(256), 0, st, items, prefix, count);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_crt_combine_grouped_n(const CrtCombineArgs* items, const int64_t* prefix, int count,
+                                               int64_t blocks, hipStream_t st) {
+  static const CrtConsts k = make_crt_consts(N);
+  hipLaunchKernelGGL((crt_combine_grouped<N>), dim3((unsigned)blocks), dim3(256), 0, st, items, prefix, count, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_crt_combine_grouped(int N, const CrtCombineArgs* items, const int64_t* prefix, int count,
+                                      int64_t blocks, hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+#define X(NN) \
+  if (N == NN) return launch_crt_combine_grouped_n<NN>(items, prefix, count, blocks, st);
+  BQ_CRT_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
 
 }  // namespace bq

@@ -285,15 +285,19 @@ int64_t crt_ldr(int64_t n) { return round_up(n, 16); }
 struct SplitLayout {
   int64_t rows_pad, cols_pad, kp;
   int S, sets;
+  int digit_sets;  // 1, or sets when every real product keeps its own digits (grouped CRT plans)
   size_t a_bytes, b_bytes, ea_bytes, eb_bytes, r_bytes;  // ea, eb, r: per set
-  size_t total() const { return a_bytes + b_bytes + size_t(sets) * (ea_bytes + eb_bytes + r_bytes); }
+  size_t total() const {
+    return size_t(digit_sets) * (a_bytes + b_bytes) + size_t(sets) * (ea_bytes + eb_bytes + r_bytes);
+  }
 };
 
-SplitLayout split_layout(const Prec& pr, int64_t m, int64_t n, int64_t k) {
+SplitLayout split_layout(const Prec& pr, int64_t m, int64_t n, int64_t k, bool grouped = false) {
   SplitLayout L{};
   const int es = pr.et == 0 ? 2 : 1;
   L.S = split_count(pr, k);
   L.sets = pr.et == 3 ? bq::kCrtProducts : 1;
+  L.digit_sets = (grouped && pr.et == 3) ? L.sets : 1;
   L.rows_pad = round_up(m, pr.et == 3 ? 256 : 128);
   L.cols_pad = round_up(n, pr.et == 3 ? 256 : 64);
   L.kp = round_up(k, pr.et == 3 ? 128 : 64);
@@ -308,11 +312,11 @@ SplitLayout split_layout(const Prec& pr, int64_t m, int64_t n, int64_t k) {
 // Workspace: pre-combined operands of P5..P8 (packed, ld = cols), plus the
 // digit buffers of one real product in the split form.
 void workspace_need(const Plan& pl, const Prec& pr, int64_t m, int64_t n, int64_t k, size_t* resident,
-                    size_t* minimum) {
+                    size_t* minimum, bool grouped = false) {
   *resident = 0;
   *minimum = 0;
   if (m == 0 || n == 0 || k == 0) return;
-  const size_t split = pr.et >= 0 ? split_layout(pr, m, n, k).total() : 0;
+  const size_t split = pr.et >= 0 ? split_layout(pr, m, n, k, grouped).total() : 0;
   bool any = false;
   for (const Prod& p : pl.prods) any |= (p.L.combo >= 0);
   if (pl.bilinear && any) {
@@ -536,9 +540,28 @@ struct Tracer {
   }
 };
 
-// Enqueue the plan.  Validation has passed.
+// Launch arguments of one problem's CRT sequence, collected instead of
+// launched (grouped CRT plans run each stage of every problem in one
+// launch).  round: index of the complex product in the plan.
+struct CrtRecord {
+  struct Split { bq::CrtSplitItem it; int N, round; };
+  struct Gemm { bq::CrtGemmItem it; int round; };
+  struct Comb { bq::CrtCombineArgs c; int N, round; };
+  struct Fill { double* p; int64_t rows, cols, ld; };
+  std::vector<bq::CombineArgs> pre;  // Hadamard pre-combinations
+  std::vector<Split> splits;
+  std::vector<Gemm> gemms;
+  std::vector<Comb> combs;
+  std::vector<Fill> fills;
+  int rounds = 0;
+};
+
+// Enqueue the plan.  Validation has passed.  With rec (CRT form only) the
+// launches are recorded, not made, and every real product of a complex
+// product keeps its own digit buffers.
 bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matrix_t* A, const bq_matrix_t* B,
-                    bq_matrix_t* C, unsigned out_mask, void* ws, bool streamed, hipStream_t s) {
+                    bq_matrix_t* C, unsigned out_mask, void* ws, bool streamed, hipStream_t s,
+                    CrtRecord* rec = nullptr) {
   const int64_t m = pl.m, n = pl.n, k = pl.k;
   if (m == 0 || n == 0) return BQ_OK;
   bool touched[8] = {};
@@ -571,10 +594,16 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   int* crt_ea[bq::kCrtProducts] = {};
   int* crt_eb[bq::kCrtProducts] = {};
   signed char* crt_res[bq::kCrtProducts] = {};
+  void* crt_da[bq::kCrtProducts] = {};
+  void* crt_db[bq::kCrtProducts] = {};
   if (pr.et >= 0 && k > 0) {
-    sl = split_layout(pr, m, n, k);
-    dig_a = wp; wp += sl.a_bytes;
-    dig_b = wp; wp += sl.b_bytes;
+    sl = split_layout(pr, m, n, k, rec != nullptr);
+    for (int q = 0; q < sl.digit_sets; ++q) {
+      crt_da[q] = wp; wp += sl.a_bytes;
+      crt_db[q] = wp; wp += sl.b_bytes;
+    }
+    dig_a = crt_da[0];
+    dig_b = crt_db[0];
     for (int q = 0; q < sl.sets; ++q) {
       crt_ea[q] = reinterpret_cast<int*>(wp); wp += sl.ea_bytes;
       crt_eb[q] = reinterpret_cast<int*>(wp); wp += sl.eb_bytes;
@@ -655,6 +684,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   // CRT form: one real product T = X Y into residue set q (exponents and
   // residue planes of its INT8 GEMMs); crt_combine reconstructs it.
   const int64_t ldr = crt_ldr(n);
+  int round = 0;  // complex product being enqueued (recorded launches carry it)
   auto crt_product = [&](const double* x1, const double* x2, double xw2, int64_t ldx, const double* y1,
                          const double* y2, double yw2, int64_t ldy, int q) -> hipError_t {
     bq::SplitArgs xa = pl.ta ? bq::SplitArgs{x1, x2, 1.0, xw2, ldx, k, m, 0, sl.rows_pad, sl.kp,
@@ -665,6 +695,16 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
                                              sl.cols_pad * sl.kp, beta, 0, 1, 1}
                              : bq::SplitArgs{y1, y2, 1.0, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp,
                                              sl.cols_pad * sl.kp, beta, 0, 0, 1};
+    if (rec) {
+      const int dq = sl.digit_sets > 1 ? q : 0;
+      rec->splits.push_back({{xa, crt_ea[q], crt_da[dq]}, S, round});
+      rec->splits.push_back({{ya, crt_eb[q], crt_db[dq]}, S, round});
+      rec->gemms.push_back({{{crt_da[dq], crt_db[dq], sl.rows_pad * sl.kp, sl.cols_pad * sl.kp, sl.kp, m, n,
+                              crt_res[q], m * ldr, ldr},
+                             S},
+                            round});
+      return hipSuccess;
+    }
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
                 double(m) * double(k) * 8.0 * (x2 ? 2 : 1) * 2.0 + double(sl.rows_pad) * double(sl.kp) * S);
@@ -704,6 +744,10 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       ndst += (ca.dst_r[j] != nullptr) + (ca.dst_i[j] != nullptr);
       for (int u = 0; u < 4; ++u) ca.w[j][u] = left ? pl.wA[q0 + j][u] : pl.wB[q0 + j][u];
     }
+    if (rec) {
+      rec->pre.push_back(ca);
+      return hipSuccess;
+    }
     Tracer tr(h, s, BQ_KERNEL_COMBINE, -1, ca.rows, ca.cols, 0, 0.0,
               double(nsrc + ndst) * double(ca.rows) * double(ca.cols) * 8.0);
     hipError_t e = bq::launch_combine(ca, s);
@@ -719,6 +763,8 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
 
   for (const Prod& p : pl.prods) {
     if (k == 0) break;
+    if (&p != &pl.prods.front()) ++round;
+    if (rec) rec->rounds = round + 1;
     Operand L = p.L, R = p.R;
     if (L.combo >= 0) {
       const int slot = streamed ? 0 : L.combo;
@@ -819,6 +865,10 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
         cc.n = n;
         cc.bits = beta;
         cc.ldc = C->ld;
+        if (rec) {
+          rec->combs.push_back({cc, S, round});
+          continue;
+        }
         int rw = 0;
         for (int q = 0; q < cc.ntgt; ++q) rw += cc.mode[q] == bq::TGT_ACCUM ? 2 : 1;
         Tracer tr(h, s, BQ_KERNEL_CRT_COMBINE, S, m, n, 0, 0.0,
@@ -880,6 +930,10 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   }
   for (int c = 0; c < 8; ++c) {
     if ((out_mask >> c & 1) && !touched[c]) {
+      if (rec) {
+        rec->fills.push_back({C->comp[c], m, n, C->ld});
+        continue;
+      }
       Tracer tr(h, s, BQ_KERNEL_FILL, -1, m, n, 0, 0.0, double(m) * double(n) * 8.0);
       hipError_t e = bq::launch_fill_zero(C->comp[c], m, n, C->ld, s);
       tr.done();
@@ -1090,8 +1144,10 @@ struct bq_grouped_plan_s {
   Prec pr;
   std::vector<bq_problem_t> probs;
   std::vector<Plan> plans;
-  std::vector<size_t> ws_off;  // FP64: each problem's pre-combination buffers
+  std::vector<size_t> ws_off;  // FP64 and CRT: each problem's own workspace region
   size_t ws_bytes = 0;
+  void* d_crt = nullptr;  // CRT: item tables of the grouped launches
+  size_t crt_bytes = 0;
   bq::GemmArgs* d_prods = nullptr;
   bq::GroupedItem* d_items = nullptr;
   int* d_counter = nullptr;
@@ -1152,6 +1208,109 @@ void tune_cache_store(const std::string& key, int cfg, int dyn) {
   f << key << " " << cfg << " " << dyn << "\n";
 }
 
+// Grouped CRT plans: every problem's CRT sequence recorded against its own
+// workspace region (base + offset), then laid out as item tables of the
+// grouped launches: the Hadamard pre-combinations of all problems, then per
+// complex product (round) the exponents of every operand, the residues (one
+// launch per modulus count), the residue GEMMs and the reconstructions (one
+// launch per modulus count).
+struct CrtLaunch {
+  enum Type { PRE, EXP, SPLIT, GEMM, COMBINE } type;
+  int N;
+  int count;
+  int64_t blocks;
+  size_t items, prefix;  // byte offsets into the table buffer
+};
+
+bq_status_t crt_record(bq_grouped_plan_t p, char* base, CrtRecord* rec) {
+  for (int i : p->order) {
+    bq_problem_t& q = p->probs[i];
+    bq_status_t st = execute(p->h, p->plans[i], p->pr, &q.A, &q.B, &q.C, 0xFFu, base + p->ws_off[i], false,
+                             nullptr, rec);
+    if (st != BQ_OK) return st;
+  }
+  return BQ_OK;
+}
+
+void crt_tables(const CrtRecord& rec, std::vector<char>* bytes, std::vector<CrtLaunch>* launches) {
+  bytes->clear();
+  launches->clear();
+  auto put = [&](const void* src, size_t n) {
+    const size_t off = align256(bytes->size());
+    bytes->resize(off + n);
+    if (n) std::memcpy(bytes->data() + off, src, n);
+    return off;
+  };
+  // Items and the prefix of their block counts; returns the launch.
+  auto add = [&](CrtLaunch::Type type, int N, const auto& items, auto blocks_of) {
+    std::vector<int64_t> prefix;
+    int64_t total = 0;
+    for (const auto& it : items) {
+      prefix.push_back(total);
+      total += blocks_of(it);
+    }
+    CrtLaunch L{type, N, int(items.size()), total, 0, 0};
+    L.items = put(items.data(), items.size() * sizeof(items[0]));
+    L.prefix = put(prefix.data(), prefix.size() * sizeof(int64_t));
+    if (L.count > 0 && L.blocks > 0) launches->push_back(L);
+  };
+  add(CrtLaunch::PRE, 0, rec.pre, [](const bq::CombineArgs& c) { return c.rows; });
+  for (int r = 0; r < rec.rounds; ++r) {
+    std::vector<CrtRecord::Split> sp;
+    for (const auto& x : rec.splits)
+      if (x.round == r) sp.push_back(x);
+    std::stable_sort(sp.begin(), sp.end(), [](const auto& a, const auto& b) { return a.N < b.N; });
+    std::vector<bq::CrtSplitItem> all;
+    for (const auto& x : sp) all.push_back(x.it);
+    add(CrtLaunch::EXP, 0, all, [](const bq::CrtSplitItem& it) { return bq::crt_exp_blocks(it.a); });
+    for (size_t i = 0; i < sp.size();) {
+      size_t j = i;
+      std::vector<bq::CrtSplitItem> part;
+      while (j < sp.size() && sp[j].N == sp[i].N) part.push_back(sp[j++].it);
+      add(CrtLaunch::SPLIT, sp[i].N, part, [](const bq::CrtSplitItem& it) { return bq::crt_split_blocks(it.a); });
+      i = j;
+    }
+    std::vector<bq::CrtGemmItem> gm;
+    for (const auto& x : rec.gemms)
+      if (x.round == r) gm.push_back(x.it);
+    add(CrtLaunch::GEMM, 0, gm, [](const bq::CrtGemmItem& it) { return bq::crt_gemm_blocks(it); });
+    std::vector<CrtRecord::Comb> cb;
+    for (const auto& x : rec.combs)
+      if (x.round == r) cb.push_back(x);
+    std::stable_sort(cb.begin(), cb.end(), [](const auto& a, const auto& b) { return a.N < b.N; });
+    for (size_t i = 0; i < cb.size();) {
+      size_t j = i;
+      std::vector<bq::CrtCombineArgs> part;
+      while (j < cb.size() && cb[j].N == cb[i].N) part.push_back(cb[j++].c);
+      add(CrtLaunch::COMBINE, cb[i].N, part, [](const bq::CrtCombineArgs& c) { return bq::crt_combine_blocks(c); });
+      i = j;
+    }
+  }
+  if (bytes->empty()) bytes->resize(256);
+}
+
+hipError_t crt_launch(const CrtLaunch& L, const char* d, hipStream_t s) {
+  const int64_t* prefix = reinterpret_cast<const int64_t*>(d + L.prefix);
+  switch (L.type) {
+    case CrtLaunch::PRE:
+      return bq::launch_grouped_combine(reinterpret_cast<const bq::CombineArgs*>(d + L.items), prefix, L.count,
+                                        L.blocks, s);
+    case CrtLaunch::EXP:
+      return bq::launch_crt_exp_grouped(reinterpret_cast<const bq::CrtSplitItem*>(d + L.items), prefix, L.count,
+                                        L.blocks, s);
+    case CrtLaunch::SPLIT:
+      return bq::launch_crt_split_grouped(L.N, reinterpret_cast<const bq::CrtSplitItem*>(d + L.items), prefix,
+                                          L.count, L.blocks, s);
+    case CrtLaunch::GEMM:
+      return bq::launch_crt_gemm_grouped(reinterpret_cast<const bq::CrtGemmItem*>(d + L.items), prefix, L.count,
+                                         L.blocks, s);
+    case CrtLaunch::COMBINE:
+      return bq::launch_crt_combine_grouped(L.N, reinterpret_cast<const bq::CrtCombineArgs*>(d + L.items), prefix,
+                                            L.count, L.blocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 // Host tables of an FP64 plan for workspace ws, copied to the device, then
 // the graph [grouped pre-combination -> persistent grouped GEMM] recorded.
 bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
@@ -1165,7 +1324,25 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
   } restore{p->h, trace};
   hipError_t e = hipSuccess;
   bq_status_t st = BQ_OK;
-  if (p->pr.et >= 0) {
+  if (p->pr.et == 3) {
+    // CRT form: the grouped launches over every problem's recorded items.
+    CrtRecord rec;
+    st = crt_record(p, static_cast<char*>(ws), &rec);
+    if (st != BQ_OK) return st;
+    std::vector<char> bytes;
+    std::vector<CrtLaunch> launches;
+    crt_tables(rec, &bytes, &launches);
+    if (bytes.size() > p->crt_bytes) return fail(BQ_ERR_INVALID_VALUE, "CRT item tables outgrew the plan");
+    e = hipMemcpy(p->d_crt, bytes.data(), bytes.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "grouped table upload");
+    e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    for (const CrtRecord::Fill& f : rec.fills)
+      if (e == hipSuccess) e = bq::launch_fill_zero(f.p, f.rows, f.cols, f.ld, p->cap);
+    for (const CrtLaunch& L : launches)
+      if (e == hipSuccess) e = crt_launch(L, static_cast<const char*>(p->d_crt), p->cap);
+    if (e != hipSuccess) st = hip_fail(e, "grouped CRT launch");
+  } else if (p->pr.et >= 0) {
     e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     // Split forms: every problem's split-precision sequence, one after another
@@ -1328,8 +1505,8 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
         return fail(BQ_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": FP64 batched plans need m, n, k > 0");
     }
     size_t res = 0, mn = 0;
-    workspace_need(pl, pr, m, n, k, &res, &mn);
-    if (pr.et < 0) {
+    workspace_need(pl, pr, m, n, k, &res, &mn, pr.et == 3);
+    if (pr.et < 0 || pr.et == 3) {
       offs[i] = total_ws;
       total_ws += res;
     } else {
@@ -1421,6 +1598,22 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
     if (e == hipSuccess) e = hipMalloc(&p->d_prefix, sizeof(int64_t) * size_t(p->ncomb));
     if (e == hipSuccess)
       e = hipMemcpy(p->d_items, items.data(), sizeof(bq::GroupedItem) * items.size(), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && pr.et == 3 && count > 0) {
+    // Table sizes do not depend on the workspace address: record against a
+    // stand-in base once to size the device buffer.
+    CrtRecord rec;
+    st = crt_record(p, reinterpret_cast<char*>(uintptr_t(1) << 20), &rec);
+    if (st != BQ_OK) {
+      bq_grouped_plan_destroy(p);
+      return st;
+    }
+    std::vector<char> bytes;
+    std::vector<CrtLaunch> launches;
+    crt_tables(rec, &bytes, &launches);
+    p->crt_bytes = bytes.size();
+    p->nitems = int(rec.gemms.size());
+    e = hipMalloc(&p->d_crt, p->crt_bytes);
   }
   if (e != hipSuccess) {
     bq_grouped_plan_destroy(p);
@@ -1525,6 +1718,7 @@ bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan) {
   if (plan->d_counter) (void)hipFree(plan->d_counter);
   if (plan->d_comb) (void)hipFree(plan->d_comb);
   if (plan->d_prefix) (void)hipFree(plan->d_prefix);
+  if (plan->d_crt) (void)hipFree(plan->d_crt);
   delete plan;
   return BQ_OK;
 }

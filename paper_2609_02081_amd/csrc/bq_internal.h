@@ -208,6 +208,41 @@ hipError_t launch_crt_split(int N, const SplitArgs& a, int* exps, void* out, hip
 hipError_t launch_crt_gemm(int N, const CrtGemmArgs& g, hipStream_t s);
 hipError_t launch_crt_combine(int N, const CrtCombineArgs& g, hipStream_t s);
 int crt_modulus(int i);
+
+// Grouped CRT launches (batched plans): every launch covers a list of items
+// of many problems; item i owns blocks [prefix[i], prefix[i + 1]) of a 1-D
+// grid, and a block finds its item by binary search in prefix.
+//   exponents: one operand per item (CrtSplitItem), crt_exp_blocks blocks;
+//   residues:  the same items, crt_split_blocks blocks (all items one N);
+//   GEMM:      one real product per item, 128 x 128 tiles x moduli;
+//   combine:   one complex product per item (all items one N).
+struct CrtSplitItem {
+  SplitArgs a;
+  int* exps;
+  void* out;
+};
+struct CrtGemmItem {
+  CrtGemmArgs g;
+  int nmod;
+};
+inline int64_t crt_exp_blocks(const SplitArgs& a) { return a.left ? a.rows : (a.cols + 63) / 64; }
+// Residues of the rows (columns) an operand has; the padding rows (columns)
+// only feed GEMM results that are never stored.
+inline int64_t crt_split_blocks(const SplitArgs& a) {
+  return a.left ? (a.rows * (a.kp / 2) + 255) / 256 : ((a.cols + 63) / 64) * (a.kp / 64);
+}
+inline int64_t crt_gemm_blocks(const CrtGemmItem& it) {
+  return ((it.g.m + 127) / 128) * ((it.g.n + 127) / 128) * it.nmod;
+}
+int64_t crt_combine_blocks(const CrtCombineArgs& c);
+hipError_t launch_crt_exp_grouped(const CrtSplitItem* items, const int64_t* prefix, int count, int64_t blocks,
+                                  hipStream_t s);
+hipError_t launch_crt_split_grouped(int N, const CrtSplitItem* items, const int64_t* prefix, int count,
+                                    int64_t blocks, hipStream_t s);
+hipError_t launch_crt_gemm_grouped(const CrtGemmItem* items, const int64_t* prefix, int count, int64_t blocks,
+                                   hipStream_t s);
+hipError_t launch_crt_combine_grouped(int N, const CrtCombineArgs* items, const int64_t* prefix, int count,
+                                      int64_t blocks, hipStream_t s);
 // Hermitian eigenproblem kernels (bq_heev.hip).
 hipError_t launch_heev_map(const HeevMapArgs& a, hipStream_t s);
 hipError_t launch_heev_merge(const double* x1, int64_t n1, double s1, const double* x2, int64_t n2, double s2, int rev,
