@@ -165,11 +165,16 @@ int bq_plan_real_gemms(unsigned maskA, unsigned maskB);
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent products C_p = op(A_p) op(B_p) of
- * different sizes in one plan.  For FP64 the plan runs as one graph: a
- * pre-combination launch for every problem, then one persistent launch whose
- * blocks take (problem, 64 x 64 tile) work items, largest problems first,
- * and run the problem's eight complex products on that tile in turn; the
- * split forms replay every problem's split-precision sequence in one graph.
+ * different sizes in one plan, run as one graph.  FP64: a pre-combination
+ * launch for every problem, then persistent launches whose blocks take
+ * (problem, 64 x 64 tile) work items, largest problems first: either one
+ * launch whose items run the problem's eight complex products on their tile
+ * in turn, or one launch per complex product (the autotuner picks).  CRT
+ * form: per complex product, one launch for each stage over every problem
+ * (exponents, residues, residue GEMMs, reconstruction; stages split by
+ * modulus count where that differs); each problem keeps its own workspace
+ * region, and every result equals the single call's bit for bit.  The
+ * digit-slice forms replay every problem's sequence in one graph.
  *
  * Pointers in the problems are baked into the plan: A, B, C of every problem
  * must stay valid (and C must not overlap any A, B or other C) until the
@@ -200,7 +205,9 @@ bq_status_t bq_grouped_plan_workspace_size(bq_grouped_plan_t plan, size_t* bytes
  * split forms it returns BQ_OK without changes. */
 bq_status_t bq_grouped_plan_autotune(bq_grouped_plan_t plan, void* ws, size_t ws_bytes, bq_stream_t stream);
 bq_status_t bq_grouped_plan_launch(bq_grouped_plan_t plan, void* ws, size_t ws_bytes, bq_stream_t stream);
-/* Chosen tile configuration, schedule (1 = dynamic counter) and work items. */
+/* Chosen tile configuration, schedule (bit 0: blocks take work items from a
+ * device counter, else cyclically; bit 1: one launch per complex product)
+ * and work items (FP64: tiles; CRT: real products). */
 bq_status_t bq_grouped_plan_info(bq_grouped_plan_t plan, int* tile_config, int* dynamic_schedule, int* work_items);
 bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan);
 

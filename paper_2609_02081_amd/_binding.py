@@ -348,7 +348,8 @@ class GroupedPlan:
     def info(self) -> dict:
         c, d, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(lib().bq_grouped_plan_info(self._plan, ctypes.byref(c), ctypes.byref(d), ctypes.byref(n)))
-        return {"tile_config": c.value, "dynamic": d.value, "work_items": n.value}
+        return {"tile_config": c.value, "dynamic": d.value & 1, "per_product_launches": d.value >> 1 & 1,
+                "work_items": n.value}
 
     def close(self):
         if self._plan:

@@ -1157,7 +1157,9 @@ struct bq_grouped_plan_s {
   int ncomb = 0;
   int64_t total_rows = 0;
   std::vector<int> order;  // problems, largest work first
-  int cfg = 0, dyn = 1;
+  int cfg = 0;
+  int dyn = 3;  // schedule bits: 1 = device work counter (else cyclic), 2 = one launch per complex product
+  std::vector<int> round_off, round_n;  // per complex product: its items after the nitems per-tile ones
   int blocks = 0;
   double flops = 0.0;
   void* bound_ws = nullptr;
@@ -1192,7 +1194,7 @@ bool tune_cache_lookup(const std::string& key, int* cfg, int* dyn) {
     std::istringstream ss(line);
     std::string k;
     int c = -1, d = -1;
-    if (ss >> k >> c >> d && k == key && (c == 0 || c == 6) && (d == 0 || d == 1)) {
+    if (ss >> k >> c >> d && k == key && (c == 0 || c == 6) && d >= 0 && d <= 3) {
       *cfg = c;
       *dyn = d;
       found = true;  // the last entry for a key wins
@@ -1432,8 +1434,15 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
     e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     e = bq::launch_grouped_combine(p->d_comb, p->d_prefix, p->ncomb, rows, p->cap);
-    if (e == hipSuccess) e = bq::launch_grouped(p->cfg, p->dyn, p->d_prods, p->d_items, p->nitems, p->d_counter,
-                                                p->blocks, p->cap);
+    if (p->dyn & 2) {
+      for (int q = 0; q < 8 && e == hipSuccess; ++q)
+        if (p->round_n[q] > 0)
+          e = bq::launch_grouped(p->cfg, p->dyn & 1, p->d_prods, p->d_items + p->nitems + p->round_off[q],
+                                 p->round_n[q], p->d_counter, p->blocks, p->cap);
+    } else if (e == hipSuccess) {
+      e = bq::launch_grouped(p->cfg, p->dyn & 1, p->d_prods, p->d_items, p->nitems, p->d_counter, p->blocks,
+                             p->cap);
+    }
     if (e != hipSuccess) st = hip_fail(e, "grouped launch");
   }
   hipGraph_t graph = nullptr;
@@ -1582,6 +1591,9 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
 
   hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
   if (e == hipSuccess && pr.et < 0 && count > 0) {
+    // Items of both schedules: (problem, tile) running the problem's complex
+    // products in turn, then per complex product q the (problem, tile) items
+    // of q alone (one launch each, so concurrent blocks share q's operands).
     std::vector<bq::GroupedItem> items;
     for (int i : p->order) {
       const int tm = int((p->plans[i].m + kGroupedTile - 1) / kGroupedTile);
@@ -1590,6 +1602,17 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
         for (int b = 0; b < tn; ++b) items.push_back({i * 8, int(p->plans[i].prods.size()), a, b});
     }
     p->nitems = int(items.size());
+    for (int q = 0; q < 8; ++q) {
+      p->round_off.push_back(int(items.size()) - p->nitems);
+      for (int i : p->order) {
+        if (q >= int(p->plans[i].prods.size())) continue;
+        const int tm = int((p->plans[i].m + kGroupedTile - 1) / kGroupedTile);
+        const int tn = int((p->plans[i].n + kGroupedTile - 1) / kGroupedTile);
+        for (int a = 0; a < tm; ++a)
+          for (int b = 0; b < tn; ++b) items.push_back({i * 8 + q, 1, a, b});
+      }
+      p->round_n.push_back(int(items.size()) - p->nitems - p->round_off.back());
+    }
     p->ncomb = 2 * count;
     e = hipMalloc(&p->d_prods, sizeof(bq::GemmArgs) * size_t(count) * 8);
     if (e == hipSuccess) e = hipMalloc(&p->d_items, sizeof(bq::GroupedItem) * items.size());
@@ -1675,7 +1698,7 @@ bq_status_t bq_grouped_plan_autotune(bq_grouped_plan_t plan, void* ws, size_t ws
   float best = 1e30f;
   int best_cfg = plan->cfg, best_dyn = plan->dyn;
   for (int c : cfgs) {
-    for (int d = 1; d >= 0; --d) {
+    for (int d : {3, 2, 1, 0}) {
       plan->cfg = c;
       plan->dyn = d;
       st = grouped_bind(plan, ws);

@@ -142,7 +142,41 @@ def test_autotune_both_schedules_and_rebind(bq, tmp_path, monkeypatch):
     plan2 = bq.GroupedPlan(probs)
     assert plan2.info()["tile_config"] == chosen["tile_config"]
     assert plan2.info()["dynamic"] == chosen["dynamic"]
+    assert plan2.info()["per_product_launches"] == chosen["per_product_launches"]
     plan2.close()
+
+
+def test_every_schedule_gives_the_same_products(bq, tmp_path, monkeypatch):
+    """Every tile configuration and schedule the autotuner chooses from,
+    forced through the tune cache (the last entry for a key wins): each
+    reads back as chosen and every product equals the default plan's to
+    1e-15 (the schedules run the same tile code in the same order)."""
+    import torch
+
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("BQ_TUNE_CACHE", str(cache))
+    probs = _batch(SMALL[:7], 64)
+    plan = bq.GroupedPlan(probs)
+    plan.autotune()
+    plan.launch()
+    torch.cuda.synchronize()
+    ref = [C.cpu().numpy().copy() for (_, _, C) in probs]
+    plan.close()
+    key = cache.read_text().split()[0]
+    for cfg in (0, 6):
+        for sched in (0, 1, 2, 3):
+            with open(cache, "a") as f:
+                f.write(f"{key} {cfg} {sched}\n")
+            p2 = bq.GroupedPlan(probs)
+            info = p2.info()
+            assert (info["tile_config"], info["dynamic"], info["per_product_launches"]) == (cfg, sched & 1, sched >> 1)
+            for (_, _, C) in probs:
+                C.fill_(float("nan"))
+            p2.launch()
+            torch.cuda.synchronize()
+            for r, (_, _, C), shape in zip(ref, probs, SMALL):
+                assert oracle.rel_frobenius(C.cpu().numpy(), r) <= 1e-15, (cfg, sched, shape)
+            p2.close()
 
 
 def _sample(n, r, seed):

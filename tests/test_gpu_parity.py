@@ -334,19 +334,21 @@ def test_large_gaussian_probe(bq):
     assert rho <= TOL
 
 
+@pytest.mark.parametrize("mask", [0xFF, 0x01])
 @pytest.mark.parametrize("k", [1040, 1031, 1024])
-def test_large_products_odd_and_ragged_k(bq, k):
-    """m = n = 2048 (1024 tiles) with k >= 1024 takes the two-deep pipeline:
-    an odd k-step count (k = 1040: 65 steps), a ragged last k-step (1031)
-    and an even count (1024), checked against the oracle on sampled rows and
-    columns (the last ones included)."""
+def test_large_products_odd_and_ragged_k(bq, k, mask):
+    """m = n = 2048 (1024 tiles) with k >= 1024 takes the two-deep pipeline
+    (complex products: k-steps of 16, real ones: of 32): odd k-step counts
+    (k = 1040: 65 or 33 steps), a ragged last k-step (1031) and an even
+    count (1024), checked against the oracle on sampled rows and columns
+    (the last ones included)."""
     import torch
 
     m = n = 2048
     rng = np.random.default_rng(70 + k)
-    A = torch.from_numpy(inputs.blocks(rng, m, k, "uniform")).to("cuda")
-    B = torch.from_numpy(inputs.blocks(rng, k, n, "uniform")).to("cuda")
-    C = bq.bq_gemm(A, B)
+    A = torch.from_numpy(inputs.blocks(rng, m, k, "uniform", mask=mask)).to("cuda")
+    B = torch.from_numpy(inputs.blocks(rng, k, n, "uniform", mask=mask)).to("cuda")
+    C = bq.bq_gemm(A, B, mask_a=mask, mask_b=mask)
     torch.cuda.synchronize()
     rows, cols = _sample(m, 40, 71), _sample(n, 40, 72)
     ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
