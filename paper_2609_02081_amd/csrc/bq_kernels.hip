@@ -533,7 +533,9 @@ grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* c
     if (it >= nitems) break;
     const GroupedItem w = items[it];
     for (int q = 0; q < w.nprod; ++q) {
-      const GemmArgs g = prods[w.prod0 + q];
+      // read in place: a private copy would sit in scratch (the epilogue
+      // indexes its targets dynamically)
+      const GemmArgs& g = prods[w.prod0 + q];
       const int64_t m0 = (int64_t)w.tm * BM, n0 = (int64_t)w.tn * BN;
       // op T / H operands are read in their stored orientation
       if (g.ta) {
