@@ -422,6 +422,7 @@ __device__ __forceinline__ double u128_to_double(unsigned __int128 u) {
 // reduction modulo 2^128.  The parts and c_i / M are staged in LDS and read
 // as broadcasts.
 constexpr int kCombineCols = 4;
+constexpr int kGroupedCombineCols = 2;  // fewer registers per thread, more waves for small products
 
 struct CrtLds {
   double cpart[kMaxCrtModuli][4];
@@ -429,23 +430,25 @@ struct CrtLds {
   double mpart[4];
 };
 
-template <int N>
+template <int N, int CC>
 __device__ __forceinline__ void crt_values(const CrtCombineArgs& g, const CrtLds& K, const signed char* res,
-                                           int64_t off, double (&out)[kCombineCols]) {
-  double x[kCombineCols][4];
-  double s[kCombineCols];
+                                           int64_t off, double (&out)[CC]) {
+  double x[CC][4];
+  double s[CC];
 #pragma unroll
-  for (int e = 0; e < kCombineCols; ++e) {
+  for (int e = 0; e < CC; ++e) {
     s[e] = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) x[e][j] = 0.0;
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const uint32_t w = *reinterpret_cast<const uint32_t*>(res + (int64_t)i * g.plane_r + off);
+    static_assert(CC == 2 || CC == 4, "one 16- or 32-bit load per plane");
+    const signed char* src = res + (int64_t)i * g.plane_r + off;
+    const uint32_t w = CC == 4 ? *reinterpret_cast<const uint32_t*>(src) : *reinterpret_cast<const uint16_t*>(src);
     const double fr = K.frac[i];
 #pragma unroll
-    for (int e = 0; e < kCombineCols; ++e) {
+    for (int e = 0; e < CC; ++e) {
       const double v = (double)(int)(signed char)(w >> (8 * e));
       s[e] = __builtin_fma(v, fr, s[e]);
 #pragma unroll
@@ -458,7 +461,7 @@ __device__ __forceinline__ void crt_values(const CrtCombineArgs& g, const CrtLds
   const __int128 M = (__int128)Mu;
   constexpr double two32 = 4294967296.0, inv32 = 1.0 / 4294967296.0;
 #pragma unroll
-  for (int e = 0; e < kCombineCols; ++e) {
+  for (int e = 0; e < CC; ++e) {
     const double q = rint(s[e]);
     uint32_t limb[4];
 #pragma unroll
@@ -494,21 +497,21 @@ __device__ __forceinline__ void crt_stage_consts(CrtLds& K, const double (&cpart
   __syncthreads();
 }
 
-// Columns c0 .. c0 + kCombineCols - 1 of row r of the reconstruction of
-// one complex product.
-template <int N>
+// Columns c0 .. c0 + CC - 1 of row r of the reconstruction of one complex
+// product.
+template <int N, int CC = kCombineCols>
 __device__ __forceinline__ void crt_combine_at(const CrtCombineArgs& g, const CrtLds& K, int64_t r, int64_t c0) {
   if (r >= g.m || c0 >= g.n) return;
-  double t[kCrtProducts][kCombineCols];
+  double t[kCrtProducts][CC];
 #pragma unroll
   for (int p = 0; p < kCrtProducts; ++p) {
 #pragma unroll
-    for (int e = 0; e < kCombineCols; ++e) t[p][e] = 0.0;
+    for (int e = 0; e < CC; ++e) t[p][e] = 0.0;
     if (p < g.np) {
-      crt_values<N>(g, K, g.res[p], r * g.ldr + c0, t[p]);
+      crt_values<N, CC>(g, K, g.res[p], r * g.ldr + c0, t[p]);
       const int ea = g.ea[p][r];
 #pragma unroll
-      for (int e = 0; e < kCombineCols; ++e) {
+      for (int e = 0; e < CC; ++e) {
         const int eb = (c0 + e < g.n) ? g.eb[p][c0 + e] : INT_MIN;
         t[p][e] = exp_special(ea) || exp_special(eb) ? exp_scaled(0.0, ea, eb, 0)
                                                       : ldexp(t[p][e], ea + eb - 2 * g.bits);
@@ -518,7 +521,7 @@ __device__ __forceinline__ void crt_combine_at(const CrtCombineArgs& g, const Cr
   for (int q = 0; q < g.ntgt; ++q) {
     double* cq = g.c[q] + r * g.ldc;
 #pragma unroll
-    for (int e = 0; e < kCombineCols; ++e) {
+    for (int e = 0; e < CC; ++e) {
       if (c0 + e >= g.n) continue;
       // zero coefficients are skipped, as the products they would scale
       double val = 0.0;
@@ -615,12 +618,12 @@ __global__ void __launch_bounds__(256) crt_combine_grouped(const CrtCombineArgs*
   crt_stage_consts<N>(K, k.cpart, k.frac, k.mpart);
   const int64_t b = blockIdx.x;
   const int i = crt_find_item(prefix, count, b);
-  // thread: one group of kCombineCols columns; groups of consecutive rows
-  // packed into the block
+  // thread: one pair of columns; the pairs of consecutive rows packed into
+  // the block
   const CrtCombineArgs& g = items[i];
-  const int64_t qpr = (g.n + kCombineCols - 1) / kCombineCols;
+  const int64_t qpr = (g.n + kGroupedCombineCols - 1) / kGroupedCombineCols;
   const int64_t q = (b - prefix[i]) * 256 + threadIdx.x;
-  crt_combine_at<N>(g, K, q / qpr, (q % qpr) * kCombineCols);
+  crt_combine_at<N, kGroupedCombineCols>(g, K, q / qpr, (q % qpr) * kGroupedCombineCols);
 }
 
 // ---------------------------------------------------------------------------
@@ -760,7 +763,7 @@ hipError_t launch_crt_combine(int N, const CrtCombineArgs& g, hipStream_t st) {
 int crt_modulus(int i) { return (i >= 0 && i < kMaxCrtModuli) ? kCrtModuli[i] : 0; }
 
 int64_t crt_combine_blocks(const CrtCombineArgs& c) {
-  return (c.m * ((c.n + kCombineCols - 1) / kCombineCols) + 255) / 256;
+  return (c.m * ((c.n + kGroupedCombineCols - 1) / kGroupedCombineCols) + 255) / 256;
 }
 
 hipError_t launch_crt_exp_grouped(const CrtSplitItem* items, const int64_t* prefix, int count, int64_t blocks,
