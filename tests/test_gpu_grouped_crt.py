@@ -130,3 +130,35 @@ def test_replays_identical_with_eager_work_between(bq):
         for p, f in zip(probs, first):
             assert np.array_equal(p["C"].cpu().numpy(), f, equal_nan=True), rep
     plan.close()
+
+
+def test_non_finite_and_long_k(bq):
+    """NaN and infinity in some rows of A and columns of B (their exponents
+    carry the non-finite marker through the atomic-free exponent kernel, so
+    the rows / columns they touch come out NaN as in a single call), and a
+    long reduced dimension (k = 20000: column exponents over 20000 rows in
+    one block, 313 k-steps per residue GEMM block) in the same batch as
+    small products."""
+    import torch
+
+    rng = np.random.default_rng(86)
+    p1 = _problem(rng, 40, 50, 30)
+    p1["A"][0][3, 7] = float("nan")
+    p1["A"][5][11, 0] = float("inf")
+    p1["B"][2][9, 4] = float("-inf")
+    p2 = _problem(rng, 24, 33, 18, "T", "H")
+    p2["B"][7][1, 2] = float("nan")
+    p3 = _problem(rng, 64, 20000, 48)
+    p4 = _problem(rng, 70, 90, 60)
+    probs = [p1, p2, p3, p4]
+    for p in (p1, p2):  # the host copies follow the device edits
+        p["a"] = np.stack([t.cpu().numpy() if t is not None else np.zeros_like(p["a"][0]) for t in p["A"]])
+        p["b"] = np.stack([t.cpu().numpy() if t is not None else np.zeros_like(p["b"][0]) for t in p["B"]])
+    plan = _check(bq, probs, oracle_check=False)
+    plan.close()
+    c1 = p1["C"].cpu().numpy()
+    assert np.isnan(c1[:, 3, :]).any() and np.isnan(c1[:, :, 4]).any()
+    assert np.isfinite(c1[:, [0, 1, 2], :][:, :, [0, 1, 2]]).all()
+    for p in (p3, p4):
+        ref = oracle.gemm(p["a"], p["b"])
+        assert oracle.rel_frobenius(p["C"].cpu().numpy(), ref) <= TOL
