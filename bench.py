@@ -100,6 +100,28 @@ def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, copy_bytes
     print(json.dumps(out))
 
 
+def summarize_trace(trace_dir, out_path):
+    """Per kernel name (first 110 characters) and grid: launches, total and
+    mean duration, registers, scratch and LDS, from a rocprofv3
+    --kernel-trace csv directory, sorted by total time (tab-separated)."""
+    import collections
+    import csv
+
+    agg = collections.defaultdict(list)
+    meta = {}
+    with open(os.path.join(trace_dir, "run_kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            key = (r["Kernel_Name"][:110], r["Grid_Size_X"], r["Grid_Size_Y"])
+            agg[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+            meta[key] = (r["VGPR_Count"], r["Accum_VGPR_Count"], r["Scratch_Size"], r["LDS_Block_Size"])
+    with open(out_path, "w") as out:
+        out.write("kernel\tgrid_x\tgrid_y\tlaunches\ttotal_ms\tavg_ms\tvgpr\tagpr\tscratch\tlds\n")
+        for key, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+            m = meta[key]
+            out.write(f"{key[0]}\t{key[1]}\t{key[2]}\t{len(v)}\t{sum(v):.3f}\t{sum(v) / len(v):.4f}\t"
+                      f"{m[0]}\t{m[1]}\t{m[2]}\t{m[3]}\n")
+
+
 class SmiSampler:
     """Socket power and graphics clocks sampled with `amd-smi metric -p -c`
     (a child process, about every half second) while a region runs.  None
@@ -481,9 +503,14 @@ def main():
                     help="products in the batched leg (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates the HBM counters)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_TSV"),
+                    help="per-kernel summary of a rocprofv3 --kernel-trace csv directory")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="turn four rocprofv3 --pmc runs (csv) into the committed traffic summary")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, copy_bytes=args.copy_calibration or (1 << 32))
         return
