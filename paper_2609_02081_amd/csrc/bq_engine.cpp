@@ -1160,6 +1160,7 @@ struct bq_grouped_plan_s {
   int cfg = 0;
   int dyn = 3;  // schedule bits: 1 = device work counter (else cyclic), 2 = one launch per complex product
   std::vector<int> round_off, round_n;  // per complex product: its items after the nitems per-tile ones
+  int ops = -1;  // 0..3: every problem has (ta, tb) = (ops >> 1, ops & 1); -1: they differ
   int blocks = 0;
   double flops = 0.0;
   void* bound_ws = nullptr;
@@ -1437,11 +1438,11 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
     if (p->dyn & 2) {
       for (int q = 0; q < 8 && e == hipSuccess; ++q)
         if (p->round_n[q] > 0)
-          e = bq::launch_grouped(p->cfg, p->dyn & 1, p->d_prods, p->d_items + p->nitems + p->round_off[q],
+          e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, p->d_prods, p->d_items + p->nitems + p->round_off[q],
                                  p->round_n[q], p->d_counter, p->blocks, p->cap);
     } else if (e == hipSuccess) {
-      e = bq::launch_grouped(p->cfg, p->dyn & 1, p->d_prods, p->d_items, p->nitems, p->d_counter, p->blocks,
-                             p->cap);
+      e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, p->d_prods, p->d_items, p->nitems, p->d_counter,
+                             p->blocks, p->cap);
     }
     if (e != hipSuccess) st = hip_fail(e, "grouped launch");
   }
@@ -1573,6 +1574,10 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
   };
   std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) { return work(a) > work(b); });
   p->blocks = 2 * std::max(1, h->cu_count);
+  for (int i = 0; i < count; ++i) {
+    const int o = 2 * int(p->plans[i].ta) + int(p->plans[i].tb);
+    p->ops = (i == 0 || p->ops == o) ? o : -1;
+  }
 
   std::ostringstream key;
   key << h->arch << ":" << h->cu_count << ":" << pr.et << ":" << pr.S << ":";

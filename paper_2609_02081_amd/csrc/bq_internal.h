@@ -185,9 +185,11 @@ int num_tile_configs();
 TileConfig tile_config(int cfg);
 int default_tile_config(int kind, int64_t m, int64_t n, int64_t k);
 // Batched form (complex x complex products only).  cfg: 0 or 6 (tile
-// configurations above); dyn: 1 = device work counter, 0 = cyclic.
-hipError_t launch_grouped(int cfg, int dyn, const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
-                          int blocks, hipStream_t s);
+// configurations above); dyn: 1 = device work counter, 0 = cyclic; ops:
+// 0..3 when every product has (ta, tb) = (ops >> 1, ops & 1) (one tile
+// variant compiled in), -1 when they differ.
+hipError_t launch_grouped(int cfg, int dyn, int ops, const GemmArgs* prods, const GroupedItem* items, int nitems,
+                          int* counter, int blocks, hipStream_t s);
 hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_prefix, int nargs, int64_t total_rows,
                                   hipStream_t s);
 // Split-precision kernels (bq_split.hip).  et: 0 = BF16 digits (beta 7),

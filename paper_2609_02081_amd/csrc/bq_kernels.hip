@@ -516,7 +516,9 @@ __global__ void reset_counter(int* counter) {
   if (threadIdx.x == 0) counter[0] = 0;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int WPE, int DYN>
+// OPS: 0..3 = every product of the plan has (ta, tb) = (OPS >> 1, OPS & 1),
+// so one tile variant is compiled in; -1 = products differ (all four).
+template <int BM, int BN, int BK, int WM, int WN, int WPE, int DYN, int OPS>
 __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter) {
@@ -538,7 +540,9 @@ grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* c
       const GemmArgs& g = prods[w.prod0 + q];
       const int64_t m0 = (int64_t)w.tm * BM, n0 = (int64_t)w.tn * BN;
       // op T / H operands are read in their stored orientation
-      if (g.ta) {
+      if constexpr (OPS >= 0) {
+        gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, (OPS >> 1), (OPS & 1)>(g, m0, n0, sm);
+      } else if (g.ta) {
         if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 1>(g, m0, n0, sm);
         else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 0>(g, m0, n0, sm);
       } else {
@@ -629,26 +633,38 @@ hipError_t launch_cgemm(int kind, const GemmArgs& g, int cfg, hipStream_t s) {
   }
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int WPE>
-static hipError_t launch_grouped_cfg(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
+template <int BM, int BN, int BK, int WM, int WN, int WPE, int OPS>
+static hipError_t launch_grouped_ops(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
                                      int dyn, int blocks, hipStream_t s) {
   constexpr int NT = (BM / WM) * (BN / WN) * 64;
   if (dyn) {
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
-    hipLaunchKernelGGL((grouped_gemm<BM, BN, BK, WM, WN, WPE, 1>), dim3(blocks), dim3(NT), 0, s, prods, items, nitems,
-                       counter);
+    hipLaunchKernelGGL((grouped_gemm<BM, BN, BK, WM, WN, WPE, 1, OPS>), dim3(blocks), dim3(NT), 0, s, prods, items,
+                       nitems, counter);
   } else {
-    hipLaunchKernelGGL((grouped_gemm<BM, BN, BK, WM, WN, WPE, 0>), dim3(blocks), dim3(NT), 0, s, prods, items, nitems,
-                       counter);
+    hipLaunchKernelGGL((grouped_gemm<BM, BN, BK, WM, WN, WPE, 0, OPS>), dim3(blocks), dim3(NT), 0, s, prods, items,
+                       nitems, counter);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_grouped(int cfg, int dyn, const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
-                          int blocks, hipStream_t s) {
+template <int BM, int BN, int BK, int WM, int WN, int WPE>
+static hipError_t launch_grouped_cfg(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter,
+                                     int dyn, int ops, int blocks, hipStream_t s) {
+  switch (ops) {
+    case 0: return launch_grouped_ops<BM, BN, BK, WM, WN, WPE, 0>(prods, items, nitems, counter, dyn, blocks, s);
+    case 1: return launch_grouped_ops<BM, BN, BK, WM, WN, WPE, 1>(prods, items, nitems, counter, dyn, blocks, s);
+    case 2: return launch_grouped_ops<BM, BN, BK, WM, WN, WPE, 2>(prods, items, nitems, counter, dyn, blocks, s);
+    case 3: return launch_grouped_ops<BM, BN, BK, WM, WN, WPE, 3>(prods, items, nitems, counter, dyn, blocks, s);
+    default: return launch_grouped_ops<BM, BN, BK, WM, WN, WPE, -1>(prods, items, nitems, counter, dyn, blocks, s);
+  }
+}
+
+hipError_t launch_grouped(int cfg, int dyn, int ops, const GemmArgs* prods, const GroupedItem* items, int nitems,
+                          int* counter, int blocks, hipStream_t s) {
   switch (cfg) {
-    case 0: return launch_grouped_cfg<64, 64, 16, 32, 32, 2>(prods, items, nitems, counter, dyn, blocks, s);
-    case 6: return launch_grouped_cfg<64, 64, 8, 32, 32, 2>(prods, items, nitems, counter, dyn, blocks, s);
+    case 0: return launch_grouped_cfg<64, 64, 16, 32, 32, 2>(prods, items, nitems, counter, dyn, ops, blocks, s);
+    case 6: return launch_grouped_cfg<64, 64, 8, 32, 32, 2>(prods, items, nitems, counter, dyn, ops, blocks, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -241,3 +241,26 @@ def test_rejects_overlapping_outputs(bq):
     with pytest.raises(bq.BqError) as e:
         bq.GroupedPlan([([Amask[0]] + [None] * 7, B, C)])
     assert e.value.code == 2
+
+
+@pytest.mark.parametrize("oa,ob", [("N", "N"), ("C", "T"), ("H", "C"), ("T", "H")])
+def test_uniform_op_batches(bq, oa, ob):
+    """Batches whose problems share one op pair run a kernel with that tile
+    variant alone; each product against the single call to 1e-15."""
+    import torch
+
+    rng = np.random.default_rng(65)
+    probs = []
+    for (m, k, n) in SMALL[:6]:
+        A = torch.from_numpy(inputs.blocks(rng, *((k, m) if oa in "TH" else (m, k)))).to("cuda")
+        B = torch.from_numpy(inputs.blocks(rng, *((n, k) if ob in "TH" else (k, n)))).to("cuda")
+        C = torch.full((8, m, n), float("nan"), dtype=torch.float64, device="cuda")
+        probs.append((A, B, C))
+    plan = bq.GroupedPlan(probs, opA=oa, opB=ob)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (A, B, C), shape in zip(probs, SMALL):
+        single = bq.bq_gemm(A, B, opA=oa, opB=ob)
+        torch.cuda.synchronize()
+        assert oracle.rel_frobenius(C.cpu().numpy(), single.cpu().numpy()) <= 1e-15, (oa, ob, shape)
+    plan.close()
