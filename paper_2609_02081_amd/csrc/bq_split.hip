@@ -50,14 +50,14 @@ __global__ void __launch_bounds__(256) split_exp_left(const SplitArgs a, int* ex
   }
 }
 
-__global__ void __launch_bounds__(256) split_exp_right(const SplitArgs a, int* exps) {
-  // grid.x = column blocks of 64, grid.y = row blocks of 1024; thread: one
-  // column, every 4th row of the block.
+__global__ void __launch_bounds__(256) split_exp_right(const SplitArgs a, int* exps, int64_t chunk) {
+  // grid.x = column blocks of 64, grid.y = row chunks of `chunk` rows;
+  // thread: one column, every 4th row of the chunk.
   const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int64_t r0 = (int64_t)blockIdx.y * 1024 + (threadIdx.x >> 6);
+  const int64_t r0 = (int64_t)blockIdx.y * chunk + (threadIdx.x >> 6);
   int e = INT_MIN;
   if (c < a.cols)
-    for (int64_t r = r0; r < a.rows && r < (int64_t)(blockIdx.y + 1) * 1024; r += 4)
+    for (int64_t r = r0; r < a.rows && r < (int64_t)(blockIdx.y + 1) * chunk; r += 4)
       e = max(e, exp_of(operand_value(a, r * a.ld + c)));
   __shared__ int red[256];
   red[threadIdx.x] = e;
@@ -835,9 +835,16 @@ hipError_t launch_split_exponents(const SplitArgs& a, int* exps, hipStream_t st)
   if (a.left)
     hipLaunchKernelGGL(split_exp_left, dim3((unsigned)a.rows, (unsigned)((a.cols + 2047) / 2048)), dim3(256), 0,
                        st, a, exps);
-  else
-    hipLaunchKernelGGL(split_exp_right, dim3((unsigned)((a.cols + 63) / 64), (unsigned)((a.rows + 1023) / 1024)),
-                       dim3(256), 0, st, a, exps);
+  else {
+    // Row chunks of up to 1024 rows, shorter where the columns alone give
+    // a small grid (about 2048 blocks, chunks of at least 64 rows).
+    const int64_t cb = (a.cols + 63) / 64;
+    const int64_t want = std::min((a.rows + 63) / 64, (2048 + cb - 1) / cb);
+    const int64_t chunks = std::max((a.rows + 1023) / 1024, std::max<int64_t>(want, 1));
+    const int64_t chunk = ((a.rows + chunks - 1) / chunks + 3) / 4 * 4;
+    hipLaunchKernelGGL(split_exp_right, dim3((unsigned)cb, (unsigned)((a.rows + chunk - 1) / chunk)), dim3(256), 0,
+                       st, a, exps, chunk);
+  }
   return hipGetLastError();
 }
 
