@@ -764,7 +764,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   for (const Prod& p : pl.prods) {
     if (k == 0) break;
     if (&p != &pl.prods.front()) ++round;
-    if (rec) rec->rounds = round + 1;
+    if (rec) rec->rounds = std::max(rec->rounds, round + 1);  // the longest plan of the batch
     Operand L = p.L, R = p.R;
     if (L.combo >= 0) {
       const int slot = streamed ? 0 : L.combo;

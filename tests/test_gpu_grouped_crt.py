@@ -162,3 +162,14 @@ def test_non_finite_and_long_k(bq):
     for p in (p3, p4):
         ref = oracle.gemm(p["a"], p["b"])
         assert oracle.rel_frobenius(p["C"].cpu().numpy(), ref) <= TOL
+
+
+def test_smallest_problem_with_fewest_products(bq):
+    """Problems are recorded largest first; the last ones here have plans
+    with fewer complex products than the first (real: one; complex: one;
+    real quaternion: eight real products), so every round of the largest
+    plan must still be launched."""
+    rng = np.random.default_rng(87)
+    probs = [_problem(rng, 96, 80, 72), _problem(rng, 40, 30, 20, mask_a=0x0F, mask_b=0x0F),
+             _problem(rng, 12, 10, 9, mask_a=0x11, mask_b=0x11), _problem(rng, 8, 8, 8, mask_a=0x01, mask_b=0x01)]
+    _check(bq, probs).close()
