@@ -328,37 +328,41 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   }
 
   // Epilogue: P from the accumulators, then coef * P into each target.
+  // Targets outer, elements inner: each target is copied into registers
+  // once (read in place from a device table, as the batched kernel does,
+  // its fields would otherwise be reloaded after every C store).
   const int64_t ldc = g.ldc;
   const double sig = sL * sR;
+  const int ntgt = g.ntgt;
+  for (int t = 0; t < ntgt; ++t) {
+    const Target T = g.tgt[t];
 #pragma unroll
-  for (int i = 0; i < MI; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < NI; ++j)
+      for (int j = 0; j < NI; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = wm0 + i * 16 + fk + 4 * v;
-        const int64_t c = wn0 + j * 16 + fr;
-        if (r >= mrem || c >= nrem) continue;
-        double pr, pi;
-        if constexpr (KIND == KIND_GAUSS) {
-          const double t1 = acc[0][i][j][v];
-          const double t2 = acc[1 % NACC][i][j][v];
-          const double t3 = acc[2 % NACC][i][j][v];
-          pr = t1 - sig * t2;
-          pi = (t3 - t1) - sig * t2;
-        } else if constexpr (KIND == KIND_RC) {
-          pr = acc[0][i][j][v];
-          pi = sR * acc[1 % NACC][i][j][v];
-        } else if constexpr (KIND == KIND_CR) {
-          pr = acc[0][i][j][v];
-          pi = sL * acc[1 % NACC][i][j][v];
-        } else {
-          pr = acc[0][i][j][v];
-          pi = 0.0;
-        }
-        const int64_t off = (m0 + r) * ldc + n0 + c;
-        for (int t = 0; t < g.ntgt; ++t) {
-          const Target& T = g.tgt[t];
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = wm0 + i * 16 + fk + 4 * v;
+          const int64_t c = wn0 + j * 16 + fr;
+          if (r >= mrem || c >= nrem) continue;
+          double pr, pi;
+          if constexpr (KIND == KIND_GAUSS) {
+            const double t1 = acc[0][i][j][v];
+            const double t2 = acc[1 % NACC][i][j][v];
+            const double t3 = acc[2 % NACC][i][j][v];
+            pr = t1 - sig * t2;
+            pi = (t3 - t1) - sig * t2;
+          } else if constexpr (KIND == KIND_RC) {
+            pr = acc[0][i][j][v];
+            pi = sR * acc[1 % NACC][i][j][v];
+          } else if constexpr (KIND == KIND_CR) {
+            pr = acc[0][i][j][v];
+            pi = sL * acc[1 % NACC][i][j][v];
+          } else {
+            pr = acc[0][i][j][v];
+            pi = 0.0;
+          }
+          const int64_t off = (m0 + r) * ldc + n0 + c;
           if (T.mode_r != TGT_SKIP) {
             double val = (T.ai == 0.0) ? T.ar * pr : ((T.ar == 0.0) ? -T.ai * pi : T.ar * pr - T.ai * pi);
             if (T.mode_r == TGT_ACCUM) val += T.cr[off];
@@ -370,7 +374,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
             T.ci[off] = val;
           }
         }
-      }
+  }
 }
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0, int DEEP = 0>
