@@ -518,23 +518,31 @@ __device__ __forceinline__ void crt_combine_at(const CrtCombineArgs& g, const Cr
       }
     }
   }
-  for (int q = 0; q < g.ntgt; ++q) {
+  // Per target, its pointer, coefficients and mode go to registers before
+  // any store (the arguments may sit in a device table the compiler cannot
+  // tell apart from C).
+  const int ntgt = g.ntgt, np = g.np;
+  const int64_t n = g.n;
+  for (int q = 0; q < ntgt; ++q) {
     double* cq = g.c[q] + r * g.ldc;
+    double w[kCrtProducts];
+#pragma unroll
+    for (int p = 0; p < kCrtProducts; ++p) w[p] = g.coef[q][p];
+    const bool accum = g.mode[q] == TGT_ACCUM;
 #pragma unroll
     for (int e = 0; e < CC; ++e) {
-      if (c0 + e >= g.n) continue;
+      if (c0 + e >= n) continue;
       // zero coefficients are skipped, as the products they would scale
       double val = 0.0;
       bool any = false;
 #pragma unroll
       for (int p = 0; p < kCrtProducts; ++p) {
-        const double w = g.coef[q][p];
-        if (p < g.np && w != 0.0) {
-          val = any ? __builtin_fma(w, t[p][e], val) : w * t[p][e];
+        if (p < np && w[p] != 0.0) {
+          val = any ? __builtin_fma(w[p], t[p][e], val) : w[p] * t[p][e];
           any = true;
         }
       }
-      if (g.mode[q] == TGT_ACCUM) val += cq[c0 + e];
+      if (accum) val += cq[c0 + e];
       cq[c0 + e] = val;
     }
   }
