@@ -173,7 +173,9 @@ int bq_plan_real_gemms(unsigned maskA, unsigned maskB);
  * form: per complex product, one launch for each stage over every problem
  * (exponents, residues, residue GEMMs, reconstruction; stages split by
  * modulus count where that differs); each problem keeps its own workspace
- * region, and every result equals the single call's bit for bit.  The
+ * region (its pre-combinations and the residues of three real products),
+ * so the plan's workspace is the sum over the problems, and every result
+ * equals the single call's bit for bit.  The
  * digit-slice forms replay every problem's sequence in one graph.
  *
  * Pointers in the problems are baked into the plan: A, B, C of every problem

@@ -1244,7 +1244,8 @@ void crt_tables(const CrtRecord& rec, std::vector<char>* bytes, std::vector<CrtL
     if (n) std::memcpy(bytes->data() + off, src, n);
     return off;
   };
-  // Items and the prefix of their block counts; returns the launch.
+  // Items and the prefix of their block counts into the buffer; the launch
+  // joins the list when it has blocks.
   auto add = [&](CrtLaunch::Type type, int N, const auto& items, auto blocks_of) {
     std::vector<int64_t> prefix;
     int64_t total = 0;
