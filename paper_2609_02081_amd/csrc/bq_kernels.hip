@@ -569,20 +569,33 @@ static const TileConfig kConfigs[] = {
     {0, 0, 0, 0, 0},         // 4: retired (spilled)
     {0, 0, 0, 0, 0},         // 5: retired (spilled)
     {64, 64, 8, 32, 32},     // 6: 4 waves, 2 waves / SIMD
+    {0, 0, 0, 0, 0},         // 7: retired (128 x 64 blocks, slower)
+    {0, 0, 0, 0, 0},         // 8: retired (128 x 64 blocks, slower)
+    {0, 0, 0, 0, 0},         // 9: retired (128 x 128 x 16, slower than 11)
+    {0, 0, 0, 0, 0},         // 10: retired (as 9, two-deep)
+    {128, 128, 32, 32, 32},  // 11: 16 waves, 4 waves / SIMD, one block per CU (real x real only)
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 int num_tile_configs() { return kNumConfigs; }
 TileConfig tile_config(int cfg) { return kConfigs[cfg]; }
 
-// Real products (one accumulator set, 64 KB of LDS per block at BK = 32)
-// take the deeper k-step: 5 % faster at n = 4096; the complex kinds keep
-// BK = 16, which leaves room for two blocks per CU.
+// Real products (one accumulator set) take k-steps of 32: 64 x 64 blocks
+// (64 KB of LDS, two per CU; 5 % faster than BK = 16 at n = 4096), or
+// 128 x 128 blocks of 16 waves (one per CU, half the bytes per flop: 10-12
+// % faster per CU) where their rounds of blocks over the 256 CUs cost less:
+// 4 small tiles per large one at 1.12x the rate, so a round of large blocks
+// costs 2 / 1.12 rounds of small ones.  The complex kinds keep BK = 16,
+// which leaves room for two blocks per CU.
 int default_tile_config(int kind, int64_t m, int64_t n, int64_t k) {
   (void)k;
-  (void)m;
-  (void)n;
-  return kind == KIND_RR ? 3 : 0;
+  if (kind != KIND_RR) return 0;
+  constexpr int64_t kCUs = 256;
+  const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
+  const int64_t t64 = ((m + 63) / 64) * ((n + 63) / 64);
+  const double rounds128 = double((t128 + kCUs - 1) / kCUs) * 2.0 / 1.12;
+  const double rounds64 = double((t64 + 2 * kCUs - 1) / (2 * kCUs));
+  return rounds128 < rounds64 ? 11 : 3;
 }
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0, int DEEP = 0>
@@ -623,6 +636,11 @@ static hipError_t launch_kind(const GemmArgs& g, int cfg, hipStream_t s) {
       }
       return launch_one<KIND, 64, 64, 32, 32, 32, 2>(g, s);
     case 6: return launch_one<KIND, 64, 64, 8, 32, 32, 2>(g, s);
+    case 11:
+      // 128 x 128 blocks for real products only (one A and one B tile in
+      // LDS: 135 KB); the complex kinds take configuration 0.
+      if constexpr (KIND == KIND_RR) return launch_one<KIND, 128, 128, 32, 32, 32, 4>(g, s);
+      return launch_kind<KIND>(g, 0, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -355,3 +355,24 @@ def test_large_products_odd_and_ragged_k(bq, k, mask):
     got = C[:, ri][:, :, ci].cpu().numpy()
     ref = oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy())
     assert oracle.rel_frobenius(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("mask", [0x01, 0x0F])
+@pytest.mark.parametrize("m,k,n", [(2040, 1001, 2040), (4100, 96, 4100), (2048, 33, 2056)])
+def test_real_products_in_large_blocks(bq, m, k, n, mask):
+    """Real x real products of this size run in 128 x 128 blocks of 16 waves
+    (k-steps of 32): ragged edge tiles in m and n, ragged and short k, real
+    and real-quaternion masks, against the oracle on sampled rows and
+    columns (the last ones included)."""
+    import torch
+
+    rng = np.random.default_rng(m + k + n + mask)
+    A = torch.from_numpy(inputs.blocks(rng, m, k, "uniform", mask=mask)).to("cuda")
+    B = torch.from_numpy(inputs.blocks(rng, k, n, "uniform", mask=mask)).to("cuda")
+    C = bq.bq_gemm(A, B, mask_a=mask, mask_b=mask)
+    torch.cuda.synchronize()
+    rows, cols = _sample(m, 40, 73), _sample(n, 40, 74)
+    ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+    got = C[:, ri][:, :, ci].cpu().numpy()
+    ref = oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy())
+    assert oracle.rel_frobenius(got, ref) <= TOL
