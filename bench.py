@@ -35,8 +35,9 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_per_launch():
-    """HBM bytes per launch from committed rocprofv3 counters, if they were
+def traffic_per_launch(key="bytes_per_launch"):
+    """HBM bytes per launch (of the GEMM, or with key="combine_bytes_per_launch"
+    of the pre-combination) from committed rocprofv3 counters, if they were
     taken on the kernel source as it is now."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -45,7 +46,7 @@ def traffic_per_launch():
         return None
     if t.get("kernel_source_sha256") != kernel_sha():
         return None
-    return t.get("bytes_per_launch")
+    return t.get(key)
 
 
 def copy_calibration(nbytes):
@@ -62,7 +63,7 @@ def copy_calibration(nbytes):
 
 
 def _pmc_rows(d, counter):
-    """(kernel name, value) per dispatch from a rocprofv3 csv output tree."""
+    """(kernel name, grid size, value) per dispatch from a rocprofv3 csv tree."""
     import csv
     import glob
 
@@ -71,30 +72,46 @@ def _pmc_rows(d, counter):
         with open(f) as fh:
             for r in csv.DictReader(fh):
                 if r.get("Counter_Name") == counter:
-                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+                    rows.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
     return rows
 
 
 def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, copy_bytes):
-    def mean_for(rows, pred):
-        v = [x for name, x in rows if pred(name)]
-        return sum(v) / len(v) if v else None
+    """HBM bytes per launch of the FP64 GEMM and of the pre-combination at the
+    benchmark size: per-dispatch FETCH_SIZE and WRITE_SIZE of the largest
+    launches of each kernel (the run also holds smaller launches of the same
+    kernels, e.g. the slab leg's), scaled by what the counters read for a
+    plain copy of copy_bytes."""
+    def mean_largest(rows, pred):
+        sel = [(g, x) for name, g, x in rows if pred(name)]
+        if not sel:
+            return None, 0
+        big = max(g for g, _ in sel)
+        v = [x for g, x in sel if g == big]
+        return sum(v) / len(v), len(v)
     is_gemm = lambda name: "cgemm_f64<0," in name
+    is_comb = lambda name: name.startswith("void bq::combine_kernel")
     is_copy = lambda name: "copy" in name.lower() or "elementwise" in name.lower()
-    f_kib = mean_for(_pmc_rows(fetch_dir, "FETCH_SIZE"), is_gemm)
-    w_kib = mean_for(_pmc_rows(write_dir, "WRITE_SIZE"), is_gemm)
-    cf = max((x for name, x in _pmc_rows(cal_fetch_dir, "FETCH_SIZE") if is_copy(name)), default=None)
-    cw = max((x for name, x in _pmc_rows(cal_write_dir, "WRITE_SIZE") if is_copy(name)), default=None)
+    fr, wr = _pmc_rows(fetch_dir, "FETCH_SIZE"), _pmc_rows(write_dir, "WRITE_SIZE")
+    f_kib, nf = mean_largest(fr, is_gemm)
+    w_kib, nw = mean_largest(wr, is_gemm)
+    cf_kib, _ = mean_largest(fr, is_comb)
+    cw_kib, _ = mean_largest(wr, is_comb)
+    cf = max((x for name, _, x in _pmc_rows(cal_fetch_dir, "FETCH_SIZE") if is_copy(name)), default=None)
+    cw = max((x for name, _, x in _pmc_rows(cal_write_dir, "WRITE_SIZE") if is_copy(name)), default=None)
     if None in (f_kib, w_kib, cf, cw):
         raise SystemExit(f"missing counters: {f_kib} {w_kib} {cf} {cw}")
     kf = copy_bytes / (cf * 1024.0)
     kw = copy_bytes / (cw * 1024.0)
     out = {"kernel": "cgemm_f64<GAUSS> (tile config 0)", "workload": "n=16384 biquaternion product",
            "kernel_source_sha256": kernel_sha(),
+           "dispatches": [nf, nw],
            "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
            "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": kf, "write_scale": kw,
-           "bytes_per_launch": f_kib * 1024.0 * kf + w_kib * 1024.0 * kw}
+           "bytes_per_launch": f_kib * 1024.0 * kf + w_kib * 1024.0 * kw,
+           "combine_bytes_per_launch": (cf_kib * 1024.0 * kf + cw_kib * 1024.0 * kw)
+           if None not in (cf_kib, cw_kib) else None}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -601,7 +618,8 @@ def main():
     combine = {"bound": "hbm", "avg_launch_ms": round(c_ms, 4), "bytes_per_launch": c_bytes,
                "achieved_GBs": round(c_bytes / (c_ms * 1e-3) / 1e9, 1) if c_ms > 0 else None,
                "peak_GBs": PEAK_HBM_GBS, "launches": len(comb),
-               "device_copy_GBs": round(copy_gbs, 1)}
+               "device_copy_GBs": round(copy_gbs, 1),
+               "traffic": traffic_per_launch("combine_bytes_per_launch")}
 
     # One GPU's share of the 8-GPU row-slab sharding: rows [0, n/8) of A and
     # C (views, so no new memory) times the whole B.
