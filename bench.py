@@ -536,8 +536,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only; run it with --gpus 1 "
-              "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+        print("bench.py measures one GPU only; run it with --gpus 1 "
+              "(sharding across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -41,7 +41,7 @@ extern "C" {
 typedef enum {
   BQ_OK = 0,
   BQ_ERR_INVALID_VALUE = 1, /* null/negative/mismatched argument            */
-  BQ_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement  */
+  BQ_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement */
   BQ_ERR_ALIAS = 3,         /* C overlaps A, B, the workspace or itself      */
   BQ_ERR_WORKSPACE = 4,     /* workspace smaller than the minimum plan       */
   BQ_ERR_HIP = 5,           /* a HIP runtime call failed                     */
