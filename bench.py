@@ -162,6 +162,7 @@ class SmiSampler:
                 first = f.readline()
             self.cmd = [sys.executable, self.exe] if first.startswith(b"#!") and b"python" in first else [self.exe]
         self.interval = interval
+        self._proc = None
         self.samples = []
         self._stop = threading.Event()
         self._thread = threading.Thread(target=self._run, daemon=True)
@@ -169,8 +170,15 @@ class SmiSampler:
     def _one(self):
         import subprocess
 
-        out = subprocess.run(self.cmd + ["metric", "-p", "-c", "--json"], capture_output=True, text=True,
-                             timeout=10).stdout
+        # The child is kept so that __exit__ can end it: none outlives the run.
+        self._proc = subprocess.Popen(self.cmd + ["metric", "-p", "-c", "--json"], stdout=subprocess.PIPE,
+                                      stderr=subprocess.DEVNULL, text=True)
+        try:
+            out, _ = self._proc.communicate(timeout=10)
+        finally:
+            if self._proc.poll() is None:
+                self._proc.kill()
+                self._proc.wait()
         g = json.loads(out)["gpu_data"][0]
         clocks = [v["clk"]["value"] for k, v in g["clock"].items()
                   if k.startswith("gfx_") and isinstance(v, dict) and isinstance(v.get("clk"), dict)]
@@ -191,8 +199,13 @@ class SmiSampler:
 
     def __exit__(self, *exc):
         self._stop.set()
+        p = self._proc
+        if p is not None and p.poll() is None:
+            p.kill()
         if self._thread.is_alive():
             self._thread.join(timeout=15)
+        if p is not None and p.poll() is None:
+            p.wait(timeout=5)
         return False
 
     def summary(self):
@@ -486,6 +499,21 @@ def batched_leg(bq, inputs, torch, count, log, split_prec=None):
     return out
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (Linux /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
 def sample_idx(n, r, seed):
     import numpy as np
 
@@ -665,11 +693,10 @@ def main():
         # sampled result agrees with the FP64 result (itself ~1e-14 from the
         # oracle) to 5e-13; the error reported is then the oracle's.  The CRT
         # form runs once at its default (the fewest moduli carrying 53 bits).
-        max_s = {"split_bf16": 8, "split_fp8": 14, "split_int8": 9, "split_int8_crt": 0}
-        start_s = {"split_bf16": 7, "split_fp8": 13, "split_int8": 7, "split_int8_crt": 0}
+        max_s = {"split_bf16": 8, "split_fp8": 13, "split_int8": 9, "split_int8_crt": 0}
         for prec in [x for x in args.split.split(",") if x]:
             tried = []
-            S = start_s[prec]
+            S = 0  # the library's default for this k first
             while True:
                 sres, _ = bq.workspace_size(n, n, n, prec=prec, slices=S)
                 sws = torch.empty(sres, dtype=torch.uint8, device=dev)
@@ -688,15 +715,17 @@ def main():
                 cs = take() if r > 0 else None
                 d = (float(np.linalg.norm(cs - samples["fp64"]) / np.linalg.norm(samples["fp64"]))
                      if r > 0 else None)
-                tried.append({"slices": S, "ms": round(sms, 1), "rel_diff_vs_fp64_sample": d})
-                log(f"{prec} S={S}: {sms:.1f} ms, rel diff vs FP64 {d}")
-                if d is None or d <= 5e-13 or S >= max_s[prec]:
+                used = next((x["config"] for x in srecs if x["kernel"] in ("slice_gemm", "crt_gemm")), S)
+                tried.append({"slices": S, "resolved_slices": used, "ms": round(sms, 1),
+                              "rel_diff_vs_fp64_sample": d})
+                log(f"{prec} S={S} ({used} used): {sms:.1f} ms, rel diff vs FP64 {d}")
+                if d is None or d <= 5e-13 or used >= max_s[prec]:
                     break
-                S += 1
+                S = used + 1
             sg = [x for x in srecs if x["kernel"] in ("slice_gemm", "crt_gemm")]
             sg_ms = sum(x["ms"] for x in sg)
-            if prec == "split_int8_crt" and sg:
-                S = sg[0]["config"]  # moduli the library chose
+            if sg:
+                S = sg[0]["config"]  # slices (moduli) the library used
             split[prec] = {"slices": S, "ms": round(sms, 2),
                            "eff_tflops": round(flop_eff / (sms * 1e-3) / 1e12, 3),
                            "speed_vs_fp64": round(ms / sms, 3), "rel_err_sampled_vs_oracle": None,
@@ -786,7 +815,7 @@ def main():
                    "kind": "oracle",
                    "sample": f"C[R,S] for {r} sampled rows R and {r} columns S (last row/column included) "
                              f"of the n={n} product, full k={n}: {t_cpu:.2f} s",
-                   "seconds": round(t_cpu, 3)}
+                   "seconds": round(t_cpu, 3), "host": host_cpu()}
             log(f"oracle {t_cpu:.1f}s, sampled rel Frobenius error {rel_err:.3e}")
         if host_checks:
             ef, es = [], []

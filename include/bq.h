@@ -38,11 +38,22 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* The enumerations below travel as 32-bit integers.  C++ gives them int as
+ * their fixed underlying type, so any integer a C caller passes is a value
+ * the library can read and reject (BQ_ERR_INVALID_VALUE) rather than an
+ * out-of-range enumeration value. */
+#ifdef __cplusplus
+#define BQ_ENUM(tag) enum tag : int
+#else
+#define BQ_ENUM(tag) enum tag
+#endif
+
+typedef BQ_ENUM(bq_status_e) {
   BQ_OK = 0,
   BQ_ERR_INVALID_VALUE = 1, /* null/negative/mismatched argument            */
   BQ_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement */
-  BQ_ERR_ALIAS = 3,         /* C overlaps A, B, the workspace or itself      */
+  BQ_ERR_ALIAS = 3,         /* C overlaps A, B, the workspace or itself, or
+                               the workspace overlaps A or B                 */
   BQ_ERR_WORKSPACE = 4,     /* workspace smaller than the minimum plan       */
   BQ_ERR_HIP = 5,           /* a HIP runtime call failed                     */
   BQ_ERR_ARCH = 6           /* device is not gfx950                          */
@@ -55,7 +66,7 @@ typedef enum {
  * n x k.  T and H read the transposed tiles straight from the stored layout
  * (no copy); the sign rules are folded into the pre-combination and the
  * combination weights. */
-typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
+typedef BQ_ENUM(bq_op_e) { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
 
 /* Arithmetic of the real GEMMs.  FP64: FP64 MFMA.  The split forms (an
  * Ozaki-style scheme; the paper itself uses FP64 throughout, Sec. III A)
@@ -64,9 +75,14 @@ typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
  * operand), multiply digit slices on low-precision MFMA with exact FP32
  * (BF16, FP8) or int32 (INT8) sums, keep the slice pairs with s + t <=
  * slices + 1, and accumulate and rescale in FP64.  Digit types: BF16
- * (beta 7, slices 1..8, default 7), OCP FP8 E4M3 (beta 4, slices 1..14,
- * default 13), INT8 (beta 7 with one bit of exponent headroom, so the
- * leading digit fits a signed byte; slices 1..9, default 7).
+ * (beta 7, slices 1..8), OCP FP8 E4M3 (beta 5 with one bit of exponent
+ * headroom h, so every digit lies in [-16, 16], exact in E4M3; slices
+ * 1..13), INT8 (beta 7 with h = 1, so the leading digit fits a signed byte;
+ * slices 1..9).  S digits carry beta S - h significand bits of a row's
+ * (column's) largest element; slices = 0 picks the fewest slices that carry
+ * 48 + ceil(log2(k) / 2) bits for the call's k (the truncation of a
+ * length-k dot product grows like sqrt(k)), capped at the maximum: at
+ * k = 16384 BF16 8, FP8 12, INT8 8 slices.
  * SPLIT_INT8_CRT is the integer-modular form (Ozaki scheme II): every row of
  * the left factor (column of the right) is scaled by a power of two to b-bit
  * integers (b <= 53, one rounding per element), the exact integer product is
@@ -80,7 +96,7 @@ typedef enum { BQ_OP_N = 0, BQ_OP_T = 1, BQ_OP_C = 2, BQ_OP_H = 3 } bq_op_t;
  * b = 0 is BQ_ERR_INVALID_VALUE.  k is limited to 133120 (int32 sums stay
  * exact).  The Hadamard and Gauss pre-combinations and the post-combination
  * stay FP64. */
-typedef enum {
+typedef BQ_ENUM(bq_prec_e) {
   BQ_PREC_FP64 = 0,
   BQ_PREC_SPLIT_BF16 = 1,
   BQ_PREC_SPLIT_FP8 = 2,
@@ -114,21 +130,31 @@ bq_status_t bq_destroy(bq_handle_t h);
 
 /* Static text for a status code (never NULL). */
 const char* bq_status_string(bq_status_t s);
-/* Text of the last failure detected by this host thread (never NULL). */
+/* Text of the last failure detected by this host thread (never NULL).  It
+ * takes no handle: failures are detected before a handle exists (bq_create)
+ * and by the handle-free calls (bq_gemm_check, bq_gemm_workspace_size), and
+ * a handle serves one host thread anyway, so the text is kept per thread. */
 const char* bq_last_error_detail(void);
 
 /* Workspace for bq_gemm.  *resident_bytes lets every pre-combined operand
  * stay in memory at once; *min_bytes is the least the streamed plan needs
  * (pre-combinations formed one product at a time).  Either output pointer
  * may be NULL.  maskA/maskB as in BQ_MASK_*.  m, n, k are the shapes of
- * op(A) (m x k) and op(B) (k x n); the sizes hold for every op. */
+ * op(A) (m x k) and op(B) (k x n); the sizes hold for every op.  The sizes
+ * depend on the shapes, masks and precision only (not on the device), so
+ * the query takes no handle and a caller can size memory before creating
+ * one. */
 bq_status_t bq_gemm_workspace_size(int64_t m, int64_t n, int64_t k,
                                    unsigned maskA, unsigned maskB,
                                    bq_prec_t prec, int slices,
                                    size_t* resident_bytes, size_t* min_bytes);
 
 /* Host-only validation of a bq_gemm call (no HIP call is made): returns what
- * bq_gemm would return for these arguments before enqueueing anything. */
+ * bq_gemm would return for these arguments before enqueueing anything.
+ * With BQ_LOG=1 in the environment, every validated call (this one and
+ * bq_gemm) prints its plan on stderr: shape, ops, masks, bilinear or
+ * component-wise form, real GEMMs, precision, slices, resident or streamed
+ * workspace. */
 bq_status_t bq_gemm_check(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
                           const bq_matrix_t* B, const bq_matrix_t* C,
                           bq_prec_t prec, int slices, const void* ws,
@@ -138,7 +164,9 @@ bq_status_t bq_gemm_check(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
  * ws: device workspace (may be NULL when bq_gemm_workspace_size gives 0);
  * with ws_bytes >= resident size the resident plan runs, otherwise with
  * ws_bytes >= min size the streamed plan, otherwise BQ_ERR_WORKSPACE.
- * m == 0 or n == 0: no-op.  k == 0: C = 0.
+ * m == 0 or n == 0: no-op.  k == 0: C = 0.  Each of m, n, k must be below
+ * 2^31 and each of op(A), op(B), C at most 2^40 elements, every ld at most
+ * 2^24 (BQ_ERR_UNSUPPORTED otherwise).
  * Components of C that are structurally zero for the given input masks are
  * written as 0.  `slices` is used by the split forms (0 = default). */
 bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB,
@@ -147,17 +175,23 @@ bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB,
                     bq_stream_t stream);
 
 /* Subalgebra special cases (Sec. III A: real, complex and real-quaternion
- * matrices embedded in H_C).  Same conventions as bq_gemm; only the named
- * components of A, B and C are read or written, the rest may be NULL.
+ * matrices embedded in H_C).  The arguments and conventions of bq_gemm (op
+ * sign rules of Sec. III, precision, slices, workspace sized by
+ * bq_gemm_workspace_size with the algebra's mask for both operands); only
+ * the named components of A, B and C are read or written, the rest may be
+ * NULL (a NULL named input component is zero).
  *   bq_re_gemm: comp[0]                     (1 real GEMM)
  *   bq_cx_gemm: comp[0] + i comp[4]         (3 real GEMMs, Gauss)
  *   bq_rq_gemm: comp[0..3] (real quaternion, 8 real GEMMs, bilinear) */
-bq_status_t bq_re_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B,
-                       bq_matrix_t* C, bq_stream_t stream);
+bq_status_t bq_re_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
+                       const bq_matrix_t* B, bq_matrix_t* C, bq_prec_t prec, int slices,
+                       void* ws, size_t ws_bytes, bq_stream_t stream);
 bq_status_t bq_cx_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
-                       const bq_matrix_t* B, bq_matrix_t* C, bq_stream_t stream);
-bq_status_t bq_rq_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B,
-                       bq_matrix_t* C, void* ws, size_t ws_bytes, bq_stream_t stream);
+                       const bq_matrix_t* B, bq_matrix_t* C, bq_prec_t prec, int slices,
+                       void* ws, size_t ws_bytes, bq_stream_t stream);
+bq_status_t bq_rq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
+                       const bq_matrix_t* B, bq_matrix_t* C, bq_prec_t prec, int slices,
+                       void* ws, size_t ws_bytes, bq_stream_t stream);
 
 /* Number of real GEMMs the planner runs for these masks (the paper's counts:
  * 24 full, 8 real quaternion, 3 complex, 1 real).  Host only. */
@@ -262,7 +296,7 @@ bq_status_t bq_heev(bq_handle_t h, const bq_matrix_t* A, double* w, double* V, i
  * and sets *count to the number copied.  `flops` and `bytes` are the
  * algorithmic work of the launch: 2 m n k per real product for a GEMM,
  * the bytes read plus written for a pre-combination or zero fill. */
-typedef enum {
+typedef BQ_ENUM(bq_kernel_e) {
   BQ_KERNEL_GEMM_GAUSS = 0, /* complex x complex, 3 real products    */
   BQ_KERNEL_GEMM_RC = 1,    /* real x complex, 2 real products       */
   BQ_KERNEL_GEMM_CR = 2,    /* complex x real, 2 real products       */

@@ -9,8 +9,9 @@ The paper computes every real GEMM in FP64; the split form is an extension
   max_j |x_ij| plus a headroom h (so |x_ij| 2^-e_i < 2^-h); right factor
   Y (k x n): per column j an exponent f_j;  h = 1 for INT8 digits (beta 7:
   without it the leading digit could reach 2^7 = 128, one past a signed
-  byte), h = 0 for BF16 (beta 7) and FP8 E4M3 (beta 4), whose leading digit
-  2^beta is representable;
+  byte) and for FP8 E4M3 digits (beta 5: every digit is then an integer in
+  [-16, 16], all of which E4M3's four significant bits hold exactly), h = 0
+  for BF16 (beta 7), whose leading digit 2^7 is representable;
 * digits of y = x 2^-e: q_1 = rint(2^b y), y_1 = y - q_1 2^-b, and
   q_s = rint(2^{bs} y_{s-1}), y_s = y_{s-1} - q_s 2^{-bs} for s = 2..S;
 * T = diag(2^e) [ sum_{s + t <= S + 1} 2^{-b(s+t)} Q_s R_t ] diag(2^f).
@@ -21,8 +22,28 @@ path only by FP64 summation order.
 """
 import numpy as np
 
-BETA = {"bf16": 7, "fp8": 4, "int8": 7}
-HEAD = {"bf16": 0, "fp8": 0, "int8": 1}
+BETA = {"bf16": 7, "fp8": 5, "int8": 7}
+HEAD = {"bf16": 0, "fp8": 1, "int8": 1}
+MAX_SLICES = {"bf16": 8, "fp8": 13, "int8": 9}
+
+
+def carried_bits(kind, S):
+    """Significand bits S digits carry for a row's largest element: the
+    scaled element lies in [2^(-1-h), 2^-h) and the remainder after S digits
+    is at most 2^(-beta S - 1), so beta S - h bits."""
+    return BETA[kind] * S - HEAD[kind]
+
+
+def default_slices(kind, k):
+    """The split form's default slice count for inner dimension k: the
+    fewest slices carrying 48 + ceil(log2(k) / 2) bits (the truncation of a
+    length-k dot product grows like sqrt(k)), at most MAX_SLICES."""
+    lg = (int(k) - 1).bit_length() if k > 1 else 0   # ceil(log2 k)
+    need = 48 + (lg + 1) // 2
+    for S in range(1, MAX_SLICES[kind] + 1):
+        if carried_bits(kind, S) >= need:
+            return S
+    return MAX_SLICES[kind]
 
 
 def exponents(X, axis, head=0):

@@ -16,8 +16,9 @@ The paper computes every real GEMM in FP64; this split form is an extension
 * T = diag(2^e) 2^(-2b) P diag(2^f), rounded to FP64.
 
 This module computes P exactly with Python integers (small sizes only), so
-its result is the correctly rounded T; the GPU reaches P through residues
-and a mixed-radix evaluation whose FP64 rounding stays within N ulps.
+its result is the correctly rounded T.  The GPU rebuilds the same integer P
+exactly from its residues (carried modulo 2^128) and rounds it to FP64 once,
+so a real product of the GPU's CRT form equals this one bit for bit.
 """
 import math
 

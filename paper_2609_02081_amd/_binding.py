@@ -65,10 +65,15 @@ _SIGS = [
     ("bq_gemm", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int,
       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
-    ("bq_re_gemm", ctypes.c_int, [ctypes.c_void_p, _M, _M, _M, ctypes.c_void_p]),
-    ("bq_cx_gemm", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_void_p]),
+    ("bq_re_gemm", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("bq_cx_gemm", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("bq_rq_gemm", ctypes.c_int,
-     [ctypes.c_void_p, _M, _M, _M, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int,
+      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("bq_plan_real_gemms", ctypes.c_int, [ctypes.c_uint, ctypes.c_uint]),
     ("bq_grouped_plan_create", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(BqProblem), ctypes.c_int, ctypes.c_int,
@@ -171,6 +176,17 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _on(stream):
+    """Context in which temporaries (workspace, outputs) are allocated: the
+    caller's stream when one is given, so that torch's caching allocator
+    hands their memory to later work only in that stream's order."""
+    import contextlib
+
+    import torch
+
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def workspace_size(m, n, k, mask_a=FULL, mask_b=FULL, prec="fp64", slices=0):
     res = ctypes.c_size_t()
     mn = ctypes.c_size_t()
@@ -195,15 +211,16 @@ def heev(A, *, mask=FULL, vectors=True, workspace=None, stream=None):
     Am = matrix(A, mask)
     n = Am.rows
     dev = (A if _is_tensor(A) else next(t for t in A if t is not None)).device
-    w = torch.empty(2 * n, dtype=torch.float64, device=dev)
-    info = torch.zeros(1, dtype=torch.int32, device=dev)
-    V = None
-    if vectors:
-        # column-major 2n x 2n complex = row-major storage of V^T
-        Vt = torch.empty((2 * n, 2 * n), dtype=torch.complex128, device=dev)
-    need = heev_workspace_size(n, _mask_of(Am), vectors, dev.index or 0)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    with _on(stream):
+        w = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        V = None
+        if vectors:
+            # column-major 2n x 2n complex = row-major storage of V^T
+            Vt = torch.empty((2 * n, 2 * n), dtype=torch.complex128, device=dev)
+        need = heev_workspace_size(n, _mask_of(Am), vectors, dev.index or 0)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     check(lib().bq_heev(handle(dev.index or 0), ctypes.byref(Am), ctypes.c_void_p(w.data_ptr()),
                         ctypes.c_void_p(Vt.data_ptr()) if vectors else None, 2 * n,
                         ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
@@ -228,13 +245,14 @@ def bq_gemm(A, B, C=None, *, opA="N", opB="N", mask_a=FULL, mask_b=FULL, prec="f
     m, k = (Am.cols, Am.rows) if opA in ("T", "H") else (Am.rows, Am.cols)
     n = Bm.rows if opB in ("T", "H") else Bm.cols
     dev = (A if _is_tensor(A) else next(t for t in A if t is not None)).device
-    if C is None:
-        C = torch.empty((8, m, n), dtype=torch.float64, device=dev)
-    Cm = matrix(C)
     res, mn = workspace_size(m, n, k, _mask_of(Am), _mask_of(Bm), prec, slices)
-    if workspace is None:
-        need = mn if streamed else res
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    with _on(stream):
+        if C is None:
+            C = torch.empty((8, m, n), dtype=torch.float64, device=dev)
+        if workspace is None:
+            need = mn if streamed else res
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    Cm = matrix(C)
     ws_bytes = workspace.numel() * workspace.element_size()
     if streamed:
         ws_bytes = min(ws_bytes, mn)
@@ -248,38 +266,44 @@ def _mask_of(M: BqMatrix) -> int:
     return sum(1 << c for c in range(8) if M.comp[c])
 
 
-def re_gemm(A, B, C, stream=None):
-    """A, B, C: (rows, cols) real tensors."""
-    z = [None] * 7
-    Am, Bm, Cm = matrix([A] + z), matrix([B] + z), matrix([C] + z)
-    check(lib().bq_re_gemm(handle(A.device.index or 0), ctypes.byref(Am), ctypes.byref(Bm),
-                           ctypes.byref(Cm), _stream(stream)))
-    return C
-
-
-def cx_gemm(A, B, C, opA="N", opB="N", stream=None):
-    """A, B, C: (re, im) pairs of real tensors."""
-    def pack(x):
-        return [x[0], None, None, None, x[1], None, None, None]
-    Am, Bm, Cm = matrix(pack(A)), matrix(pack(B)), matrix(pack(C))
-    check(lib().bq_cx_gemm(handle(A[0].device.index or 0), OPS[opA], OPS[opB], ctypes.byref(Am),
-                           ctypes.byref(Bm), ctypes.byref(Cm), _stream(stream)))
-    return C
-
-
-def rq_gemm(A, B, C, workspace=None, stream=None):
-    """A, B, C: lists of 4 real tensors (units 1, i, j, k)."""
+def _sub_gemm(name, mask, comps_a, comps_b, comps_c, opA, opB, prec, slices, workspace, stream):
+    """Shared marshalling of the subalgebra entry points: 8-slot component
+    lists with the algebra's components in place, the rest None."""
     import torch
 
+    Am, Bm, Cm = matrix(comps_a, mask), matrix(comps_b, mask), matrix(comps_c, mask)
+    dev = next(t for t in comps_c if t is not None).device
+    m, k = (Am.cols, Am.rows) if opA in ("T", "H") else (Am.rows, Am.cols)
+    n = Bm.rows if opB in ("T", "H") else Bm.cols
+    if workspace is None:
+        res, _ = workspace_size(m, n, k, mask, mask, prec, slices)
+        with _on(stream):
+            workspace = torch.empty(max(res, 1), dtype=torch.uint8, device=dev)
+    check(getattr(lib(), name)(handle(dev.index or 0), OPS[opA], OPS[opB], ctypes.byref(Am), ctypes.byref(Bm),
+                               ctypes.byref(Cm), PRECS[prec], slices, ctypes.c_void_p(workspace.data_ptr()),
+                               workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def re_gemm(A, B, C, opA="N", opB="N", prec="fp64", slices=0, workspace=None, stream=None):
+    """A, B, C: (rows, cols) real tensors (component 1 alone)."""
+    z = [None] * 7
+    _sub_gemm("bq_re_gemm", REAL, [A] + z, [B] + z, [C] + z, opA, opB, prec, slices, workspace, stream)
+    return C
+
+
+def cx_gemm(A, B, C, opA="N", opB="N", prec="fp64", slices=0, workspace=None, stream=None):
+    """A, B, C: (re, im) pairs of real tensors (components 1 and 5)."""
+    def pack(x):
+        return [x[0], None, None, None, x[1], None, None, None]
+    _sub_gemm("bq_cx_gemm", COMPLEX, pack(A), pack(B), pack(C), opA, opB, prec, slices, workspace, stream)
+    return C
+
+
+def rq_gemm(A, B, C, opA="N", opB="N", prec="fp64", slices=0, workspace=None, stream=None):
+    """A, B, C: lists of 4 real tensors (units 1, i, j, k)."""
     def pack(x):
         return list(x) + [None] * 4
-    Am, Bm, Cm = matrix(pack(A)), matrix(pack(B)), matrix(pack(C))
-    res, _ = workspace_size(Am.rows, Bm.cols, Am.cols, REAL_QUAT, REAL_QUAT)
-    if workspace is None:
-        workspace = torch.empty(max(res, 1), dtype=torch.uint8, device=A[0].device)
-    check(lib().bq_rq_gemm(handle(A[0].device.index or 0), ctypes.byref(Am), ctypes.byref(Bm),
-                           ctypes.byref(Cm), ctypes.c_void_p(workspace.data_ptr()),
-                           workspace.numel(), _stream(stream)))
+    _sub_gemm("bq_rq_gemm", REAL_QUAT, pack(A), pack(B), pack(C), opA, opB, prec, slices, workspace, stream)
     return C
 
 

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbq.so")
-SOURCES = ["bq_engine.cpp", "bq_kernels.hip", "bq_split.hip", "bq_crt.hip", "bq_heev.hip"]
+SOURCES = ["bq_engine.cpp", "bq_kernels.hip", "bq_split.hip", "bq_split_f8.hip", "bq_crt.hip", "bq_heev.hip"]
 # The eigensolves of bq_heev call rocSOLVER (with rocBLAS for its handle).
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -40,14 +40,20 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        _run([HIPCC, *COMMON, *EXTRA.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([HIPCC, *COMMON, *EXTRA.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # One compiler process per source, at most as many as there are CPUs.
+    with ThreadPoolExecutor(max_workers=max(1, min(len(cmds), os.cpu_count() or 1, 8))) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp], verbose)
     os.replace(tmp, LIB)

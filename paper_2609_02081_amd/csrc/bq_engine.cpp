@@ -211,13 +211,12 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Arithmetic of the real GEMMs: et = -1 FP64 MFMA, else the digit type of
 // the split form (0 BF16, 1 FP8, 2 INT8) with S slices, or 3 for the CRT
-// form with S moduli (S = 0: chosen from k by crt_default_moduli).
+// form with S moduli (S = 0: chosen from k by digit_default_slices or
+// crt_default_moduli).
 struct Prec {
   int et = -1;
   int S = 0;
 };
-
-constexpr int kDefaultSlices[3] = {7, 13, 7};
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -266,9 +265,28 @@ int crt_default_moduli(int64_t k) {
   return bq::kMaxCrtModuli;
 }
 
+// Default slice count of a digit form (slices = 0).  S digits of beta bits
+// under an exponent with headroom h carry beta S - h significand bits of a
+// row's (column's) largest element.  The truncation of a length-k dot
+// product (the dropped digit pairs and the remainders, one term per k
+// element, of random sign) grows like sqrt(k) 2^-(beta S - h) times the row
+// and column maxima, so the default asks for 48 + ceil(log2(k) / 2) bits:
+// 55 at k = 16384, where the sampled error of the Hermitian workload is
+// about 1e-13 2^(56 - bits) (below 5e-13 at 55 bits); the fewest slices
+// that carry them, capped at the digit type's maximum.
+int digit_default_slices(int et, int64_t k) {
+  const int lg = k > 1 ? 64 - __builtin_clzll(uint64_t(k - 1)) : 0;  // ceil(log2 k)
+  const int need = 48 + (lg + 1) / 2;
+  const int b = bq::slice_beta(et), h = bq::slice_head(et), smax = bq::max_slices(et);
+  for (int S = 1; S <= smax; ++S)
+    if (b * S - h >= need) return S;
+  return smax;
+}
+
 // Slices (moduli) one real product of inner dimension k uses.
 int split_count(const Prec& pr, int64_t k) {
-  return (pr.et == 3 && pr.S == 0) ? crt_default_moduli(k) : pr.S;
+  if (pr.S != 0 || pr.et < 0) return pr.S;
+  return pr.et == 3 ? crt_default_moduli(k) : digit_default_slices(pr.et, k);
 }
 
 // Largest padded k of the CRT GEMM (k is padded to 128): kp 127^2 < 2^31
@@ -309,6 +327,18 @@ SplitLayout split_layout(const Prec& pr, int64_t m, int64_t n, int64_t k, bool g
   return L;
 }
 
+// Size limits of a product: each dimension below 2^31 and each matrix
+// (op(A) m x k, op(B) k x n, C m x n) at most 2^40 elements (8 TiB per
+// block).  Within them every workspace and address computation fits 64 bits.
+constexpr int64_t kMaxDim = (int64_t(1) << 31) - 1;
+constexpr int64_t kMaxElems = int64_t(1) << 40;
+
+bool too_large(int64_t m, int64_t n, int64_t k) {
+  if (m > kMaxDim || n > kMaxDim || k > kMaxDim) return true;
+  auto big = [](int64_t a, int64_t b) { return a > 0 && b > kMaxElems / a; };
+  return big(m, k) || big(k, n) || big(m, n);
+}
+
 // Workspace: pre-combined operands of P5..P8 (packed, ld = cols), plus the
 // digit buffers of one real product in the split form.
 void workspace_need(const Plan& pl, const Prec& pr, int64_t m, int64_t n, int64_t k, size_t* resident,
@@ -346,7 +376,7 @@ bq_status_t prec_of(bq_prec_t prec, int slices, Prec* out) {
       return fail(BQ_ERR_INVALID_VALUE, "moduli above " + std::to_string(bq::kMaxCrtModuli));
     p.S = slices;
   } else if (p.et >= 0) {
-    p.S = slices == 0 ? kDefaultSlices[p.et] : slices;
+    p.S = slices;  // 0: chosen from k by digit_default_slices
     if (p.S > bq::max_slices(p.et))
       return fail(BQ_ERR_INVALID_VALUE, "slices above " + std::to_string(bq::max_slices(p.et)) +
                                             " for this digit type");
@@ -385,6 +415,36 @@ Range block_range(const double* p, int64_t rows, int64_t cols, int64_t ld) {
 
 bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) != 0; }
 
+// Planner log (BQ_LOG=1): one line per validated call on stderr.
+bool log_enabled() {
+  const char* e = std::getenv("BQ_LOG");
+  return e && e[0] == '1';
+}
+
+unsigned mask_of(const bq_matrix_t* M) {
+  unsigned m = 0;
+  for (int c = 0; c < 8; ++c) m |= (M->comp[c] != nullptr) << c;
+  return m;
+}
+
+void log_plan(const Plan& pl, const Prec& pr, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
+              const bq_matrix_t* B, bool streamed, size_t ws_used) {
+  static const char* kOp = "NTCH";
+  static const char* kPrec[5] = {"split_bf16", "split_fp8", "split_int8", "split_int8_crt", "?"};
+  const char* prec = pr.et < 0 ? "fp64" : kPrec[std::min(pr.et, 4)];
+  int nprod = 0, ncombo = 0;
+  for (const Prod& p : pl.prods) {
+    ++nprod;
+    ncombo += p.L.combo >= 0;
+  }
+  std::fprintf(stderr,
+               "[bq] plan m=%lld n=%lld k=%lld op=%c%c maskA=0x%02x maskB=0x%02x form=%s real_gemms=%d "
+               "complex_products=%d hadamard=%d prec=%s slices=%d workspace=%s %zu B\n",
+               (long long)pl.m, (long long)pl.n, (long long)pl.k, kOp[opA & 3], kOp[opB & 3], mask_of(A), mask_of(B),
+               pl.bilinear ? "bilinear" : "componentwise", pl.real_gemms, nprod, ncombo, prec,
+               pr.et >= 0 ? split_count(pr, pl.k) : 0, streamed ? "streamed" : "resident", ws_used);
+}
+
 // Validation shared by every entry point.  out_mask: output components the
 // call writes (all of them must be non-null).
 bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
@@ -417,6 +477,8 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
   const int64_t kb = op_trans(opB) ? B->cols : B->rows, n = op_trans(opB) ? B->rows : B->cols;
   if (k != kb) return fail(BQ_ERR_INVALID_VALUE, "inner dimensions of op(A) and op(B) differ");
   if (C->rows != m || C->cols != n) return fail(BQ_ERR_INVALID_VALUE, "C must be rows(op(A)) x cols(op(B))");
+  if (too_large(m, n, k))
+    return fail(BQ_ERR_UNSUPPORTED, "a dimension above 2^31 - 1 or a matrix above 2^40 elements");
   if (pr.et == 3 && k > 0) {
     if (round_up(k, 128) > kCrtMaxK)
       return fail(BQ_ERR_UNSUPPORTED, "CRT form: k above " + std::to_string(kCrtMaxK) + " is not supported");
@@ -452,8 +514,14 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
     }
     const size_t used_ws = use_stream ? mn : res;
     if (check_ws && ws && used_ws > 0) {
+      // The part of the workspace the plan writes must not hold an input:
+      // the pre-combination and the digit splits would overwrite it before
+      // the GEMMs read it.
       const uintptr_t lo = reinterpret_cast<uintptr_t>(ws);
-      ins.push_back({lo, lo + used_ws});
+      const Range wr{lo, lo + used_ws};
+      for (const Range& r : ins)
+        if (overlaps(wr, r)) return fail(BQ_ERR_ALIAS, "the workspace overlaps a component of A or B");
+      ins.push_back(wr);
     }
     for (size_t i = 0; i < outs.size(); ++i) {
       for (const Range& r : ins)
@@ -462,6 +530,7 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
         if (overlaps(outs[i], outs[j])) return fail(BQ_ERR_ALIAS, "two components of C overlap");
     }
   }
+  if (log_enabled()) log_plan(plan, pr, opA, opB, A, B, use_stream, check_ws ? (use_stream ? mn : res) : 0);
   if (plan_out) *plan_out = std::move(plan);
   if (streamed) *streamed = use_stream;
   if (prec_out) *prec_out = pr;
@@ -1072,6 +1141,8 @@ const char* bq_last_error_detail(void) { return g_detail.c_str(); }
 bq_status_t bq_gemm_workspace_size(int64_t m, int64_t n, int64_t k, unsigned maskA, unsigned maskB,
                                    bq_prec_t prec, int slices, size_t* resident_bytes, size_t* min_bytes) {
   if (m < 0 || n < 0 || k < 0) return fail(BQ_ERR_INVALID_VALUE, "negative dimension");
+  if (too_large(m, n, k))
+    return fail(BQ_ERR_UNSUPPORTED, "a dimension above 2^31 - 1 or a matrix above 2^40 elements");
   if (maskA > 0xFFu || maskB > 0xFFu) return fail(BQ_ERR_INVALID_VALUE, "mask has bits above 7");
   Prec pr;
   if (bq_status_t ps = prec_of(prec, slices, &pr); ps != BQ_OK) return ps;
@@ -1113,28 +1184,30 @@ bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* 
   return run(h, opA, opB, A, B, C, prec, slices, ws, ws_bytes, 0xFFu, stream);
 }
 
-bq_status_t bq_re_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C,
-                       bq_stream_t stream) {
+// The subalgebra entry points: bq_gemm with the inputs and the output
+// restricted to the algebra's components (the others are neither read nor
+// written and may be NULL).
+static bq_status_t run_sub(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                           bq_matrix_t* C, bq_prec_t prec, int slices, void* ws, size_t ws_bytes, unsigned mask,
+                           bq_stream_t stream) {
   if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
-  bq_matrix_t a = restrict_to(A, BQ_MASK_REAL), b = restrict_to(B, BQ_MASK_REAL), c = restrict_to(C, BQ_MASK_REAL);
-  if (!a.comp[0] || !b.comp[0]) return fail(BQ_ERR_INVALID_VALUE, "bq_re_gemm needs comp[0] of A and B");
-  return run(h, BQ_OP_N, BQ_OP_N, &a, &b, &c, BQ_PREC_FP64, 0, nullptr, 0, BQ_MASK_REAL, stream);
+  bq_matrix_t a = restrict_to(A, mask), b = restrict_to(B, mask), c = restrict_to(C, mask);
+  return run(h, opA, opB, &a, &b, &c, prec, slices, ws, ws_bytes, mask, stream);
+}
+
+bq_status_t bq_re_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                       bq_matrix_t* C, bq_prec_t prec, int slices, void* ws, size_t ws_bytes, bq_stream_t stream) {
+  return run_sub(h, opA, opB, A, B, C, prec, slices, ws, ws_bytes, BQ_MASK_REAL, stream);
 }
 
 bq_status_t bq_cx_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
-                       bq_matrix_t* C, bq_stream_t stream) {
-  if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
-  bq_matrix_t a = restrict_to(A, BQ_MASK_COMPLEX), b = restrict_to(B, BQ_MASK_COMPLEX),
-              c = restrict_to(C, BQ_MASK_COMPLEX);
-  return run(h, opA, opB, &a, &b, &c, BQ_PREC_FP64, 0, nullptr, 0, BQ_MASK_COMPLEX, stream);
+                       bq_matrix_t* C, bq_prec_t prec, int slices, void* ws, size_t ws_bytes, bq_stream_t stream) {
+  return run_sub(h, opA, opB, A, B, C, prec, slices, ws, ws_bytes, BQ_MASK_COMPLEX, stream);
 }
 
-bq_status_t bq_rq_gemm(bq_handle_t h, const bq_matrix_t* A, const bq_matrix_t* B, bq_matrix_t* C, void* ws,
-                       size_t ws_bytes, bq_stream_t stream) {
-  if (!A || !B || !C) return fail(BQ_ERR_INVALID_VALUE, "A, B and C must be non-null");
-  bq_matrix_t a = restrict_to(A, BQ_MASK_REAL_QUATERNION), b = restrict_to(B, BQ_MASK_REAL_QUATERNION),
-              c = restrict_to(C, BQ_MASK_REAL_QUATERNION);
-  return run(h, BQ_OP_N, BQ_OP_N, &a, &b, &c, BQ_PREC_FP64, 0, ws, ws_bytes, BQ_MASK_REAL_QUATERNION, stream);
+bq_status_t bq_rq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                       bq_matrix_t* C, bq_prec_t prec, int slices, void* ws, size_t ws_bytes, bq_stream_t stream) {
+  return run_sub(h, opA, opB, A, B, C, prec, slices, ws, ws_bytes, BQ_MASK_REAL_QUATERNION, stream);
 }
 
 }  // extern "C"
@@ -1889,13 +1962,6 @@ bool heev_layout(rocblas_handle rb, int64_t n, unsigned mask, bool vectors, Heev
   l.total = off;
   *L = l;
   return true;
-}
-
-unsigned mask_of(const bq_matrix_t* M) {
-  unsigned m = 0;
-  for (int c = 0; c < 8; ++c)
-    if (M->comp[c]) m |= 1u << c;
-  return m;
 }
 
 }  // namespace

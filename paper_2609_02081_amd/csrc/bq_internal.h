@@ -192,12 +192,17 @@ hipError_t launch_grouped(int cfg, int dyn, int ops, const GemmArgs* prods, cons
                           int* counter, int blocks, hipStream_t s);
 hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_prefix, int nargs, int64_t total_rows,
                                   hipStream_t s);
-// Split-precision kernels (bq_split.hip).  et: 0 = BF16 digits (beta 7),
-// 1 = OCP FP8 E4M3 digits (beta 4), 2 = INT8 digits (beta 7, headroom 1).
+// Split-precision kernels (bq_split.hip, bq_split_f8.hip).  et: 0 = BF16
+// digits (beta 7), 1 = OCP FP8 E4M3 digits (beta 5, headroom 1), 2 = INT8
+// digits (beta 7, headroom 1).
 hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t s);
 // Row (a.left) or column exponents of a split operand into exps.
 hipError_t launch_split_exponents(const SplitArgs& a, int* exps, hipStream_t s);
 hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t s);  // variant -1: default
+// FP8 digits (bq_split_f8.hip): beta 5, headroom 1, 1..13 slices.
+hipError_t launch_slice_gemm_f8(int S, const SliceGemmArgs& g, hipStream_t s);
+int f8_beta();
+int f8_head();
 int resolve_slice_variant(int et, int S, int variant);  // the shape launch_slice_gemm runs
 int slice_variant_tiled(int variant);                    // digit layout the shape reads (SplitArgs::tiled)
 int max_slices(int et);

@@ -210,15 +210,6 @@ struct SliceTraits<0> {  // BF16 digits, v_mfma_f32_16x16x32_bf16
   }
 };
 template <>
-struct SliceTraits<1> {  // OCP FP8 E4M3 digits, v_mfma_f32_16x16x32_fp8_fp8
-  static constexpr int ES = 1, KSTEP = 32, CH = 8, BETA = 4;
-  typedef long frag_t;
-  typedef f4 acc_t;
-  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
-  }
-};
-template <>
 struct SliceTraits<2> {  // INT8 digits, v_mfma_i32_16x16x64_i8 (exact int32 sums)
   static constexpr int ES = 1, KSTEP = 64, CH = 16, BETA = 7;
   typedef i4v frag_t;
@@ -886,30 +877,33 @@ static hipError_t launch_slice_v(const SliceGemmArgs& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Default: the direct-to-LDS shape for BF16 and INT8 digits; for FP8 the
-// 8-wave shape while it fits 256 registers, then the persistent-level one.
-int default_slice_variant(int et, int S) { return et != 1 ? 3 : (S <= 8 ? 0 : 2); }
+// Default: the direct-to-LDS shape for BF16 and INT8 digits.  FP8 digits
+// have one shape, slice_gemm_f8 (variant 5, bq_split_f8.hip).
+int default_slice_variant(int et, int S) {
+  (void)S;
+  return et == 1 ? 5 : 3;
+}
 
 int resolve_slice_variant(int et, int S, int variant) {
+  if (et == 1) return 5;
   if (variant < 0 || variant > 4) return default_slice_variant(et, S);
-  if (variant >= 3 && et == 1) return default_slice_variant(et, S);
   if (variant == 4 && S > 8) return 3;  // the 32 x 32 shape is built up to 8 slices
-  if (variant == 0 && S > (et == 1 ? 8 : 6)) return default_slice_variant(et, S);
+  if (variant == 0 && S > 6) return default_slice_variant(et, S);
   return variant;
 }
 
-int slice_variant_tiled(int variant) { return variant == 3 ? 1 : (variant == 4 ? 2 : 0); }
+int slice_variant_tiled(int variant) { return (variant == 3 || variant == 5) ? 1 : (variant == 4 ? 2 : 0); }
 
 template <int ET, int S>
 static hipError_t launch_slice_s(const SliceGemmArgs& g, int variant, hipStream_t st) {
   variant = resolve_slice_variant(ET, S, variant);
   if (variant == 0) {
-    if constexpr (ET == 1 ? S <= 8 : S <= 6) return launch_slice_v<ET, S, 0>(g, st);
+    if constexpr (S <= 6) return launch_slice_v<ET, S, 0>(g, st);
     else return hipErrorInvalidValue;
   }
   if (variant == 2) return launch_slice_v<ET, S, 2>(g, st);
   if (variant == 4) {
-    if constexpr (ET != 1 && S <= 8) {
+    if constexpr (S <= 8) {
       const int64_t tiles = ((g.m + 127) / 128) * ((g.n + 63) / 64);
       if (tiles <= 0) return hipSuccess;
       if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
@@ -920,15 +914,11 @@ static hipError_t launch_slice_s(const SliceGemmArgs& g, int variant, hipStream_
     }
   }
   if (variant == 3) {
-    if constexpr (ET != 1) {
-      const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
-      if (tiles <= 0) return hipSuccess;
-      if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((slice_gemm_dma<ET, S>), dim3((unsigned)tiles), dim3(256), 0, st, g);
-      return hipGetLastError();
-    } else {
-      return hipErrorInvalidValue;
-    }
+    const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
+    if (tiles <= 0) return hipSuccess;
+    if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((slice_gemm_dma<ET, S>), dim3((unsigned)tiles), dim3(256), 0, st, g);
+    return hipGetLastError();
   }
   return launch_slice_v<ET, S, 1>(g, st);
 }
@@ -940,20 +930,19 @@ int slice_block_rows(int et, int S) {
 }
 
 int slice_kstep(int et) {
-  return et == 0 ? SliceTraits<0>::KSTEP : (et == 1 ? SliceTraits<1>::KSTEP : SliceTraits<2>::KSTEP);
+  return et == 0 ? SliceTraits<0>::KSTEP : (et == 1 ? 64 : SliceTraits<2>::KSTEP);
 }
-int slice_beta(int et) {
-  return et == 0 ? SliceTraits<0>::BETA : (et == 1 ? SliceTraits<1>::BETA : SliceTraits<2>::BETA);
-}
-int slice_head(int et) { return et == 2 ? 1 : 0; }
+int slice_beta(int et) { return et == 0 ? SliceTraits<0>::BETA : (et == 1 ? f8_beta() : SliceTraits<2>::BETA); }
+int slice_head(int et) { return et == 0 ? 0 : (et == 1 ? f8_head() : 1); }
 
 // Level sums stay exact while every partial sum is an integer below 2^24
 // (FP32) or 2^31 (int32).  Digit bounds: |q_1| <= 2^{b-h}, |q_s| <= 2^{b-1};
-// a level d = s + t has at most d - 1 pairs, two of them with a leading
-// digit, so per k element |level| <= 2^{2b-2} max(4, d + 1) <= 2^{2b-2} (S + 3).
+// a level d = s + t has at most d - 1 <= S pairs.  With h = 1 every digit is
+// within 2^{b-1}, so per k element |level| <= 2^{2b-2} S; with h = 0 the two
+// pairs holding a leading digit count twice: |level| <= 2^{2b-2} (S + 3).
 int slice_flush_steps(int et, int S) {
   const int b = slice_beta(et);
-  const double per_k = std::ldexp(1.0, 2 * b - 2) * (S + 3);
+  const double per_k = std::ldexp(1.0, 2 * b - 2) * (slice_head(et) ? S : S + 3);
   const double lim = et == 2 ? 2147483647.0 : 16777216.0;
   const int64_t kmax = (int64_t)(lim / per_k);
   const int64_t steps = kmax / slice_kstep(et);
@@ -963,7 +952,7 @@ int slice_flush_steps(int et, int S) {
 #define BQ_SPLIT_CASES(ET, X) \
   X(ET, 1) X(ET, 2) X(ET, 3) X(ET, 4) X(ET, 5) X(ET, 6) X(ET, 7) X(ET, 8)
 #define BQ_SPLIT_CASES_MORE(X) \
-  X(1, 9) X(1, 10) X(1, 11) X(1, 12) X(1, 13) X(1, 14) X(2, 9)
+  X(1, 9) X(1, 10) X(1, 11) X(1, 12) X(1, 13) X(2, 9)
 
 hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t st) {
 #define X(E, SS) \
@@ -977,18 +966,18 @@ hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out,
 }
 
 hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t st) {
+  if (et == 1) return launch_slice_gemm_f8(S, g, st);
 #define X(E, SS) \
   if (et == E && S == SS) return launch_slice_s<E, SS>(g, variant, st);
   BQ_SPLIT_CASES(0, X)
-  BQ_SPLIT_CASES(1, X)
   BQ_SPLIT_CASES(2, X)
-  BQ_SPLIT_CASES_MORE(X)
+  X(2, 9)
 #undef X
   return hipErrorInvalidValue;
 }
 
 
 
-int max_slices(int et) { return et == 0 ? 8 : (et == 1 ? 14 : 9); }
+int max_slices(int et) { return et == 0 ? 8 : (et == 1 ? 13 : 9); }
 
 }  // namespace bq

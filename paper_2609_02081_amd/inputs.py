@@ -156,6 +156,23 @@ def device_uniform(n_rows: int, n_cols: int, seed: int, device, count: int = 8):
     return t
 
 
+def device_logspread(n_rows: int, n_cols: int, seed: int, device, count: int = 8):
+    """(count, rows, cols) float64 sign * 10^U(-6, 6) drawn on `device` (the
+    log-spread recipe at sizes the host would take long to draw)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    t = torch.empty((count, n_rows, n_cols), dtype=torch.float64, device=device)
+    t.uniform_(-6.0, 6.0, generator=g)
+    torch.pow(10.0, t, out=t)
+    sign = torch.empty((count, n_rows, n_cols), dtype=torch.float64, device=device)
+    sign.uniform_(-1.0, 1.0, generator=g)
+    t.mul_(torch.sign(sign))
+    del sign
+    return t
+
+
 def hermitian_pair(n: int, seed: int, device="cpu"):
     """A Fock-like (signed spectrum, `seed`) and B density-like (positive
     spectrum, `seed + 1`) Hermitian biquaternions, each (8, n, n)."""

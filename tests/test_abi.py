@@ -115,7 +115,7 @@ def test_ops_and_precisions():
     res_bf, _ = B.workspace_size(4, 4, 4, 0xFF, 0xFF, "split_bf16", 0)
     assert check(A, Bm, C, prec=1, ws=4 * FAKE, ws_bytes=res_bf) == OK
     assert check(A, Bm, C, prec=1, slices=9, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
-    assert check(A, Bm, C, prec=2, slices=15, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
+    assert check(A, Bm, C, prec=2, slices=14, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
     assert check(A, Bm, C, prec=3, slices=10, ws=4 * FAKE, ws_bytes=1 << 30) == INVALID
 
 
@@ -130,6 +130,20 @@ def test_alias_detection():
     # two components of C overlapping each other
     assert check(A, mat(k, n, 2 * FAKE), mat(m, n, 3 * FAKE, stride=64), ws=4 * FAKE,
                  ws_bytes=res) == ALIAS
+    # the workspace overlapping a component of A or of B (the pre-combination
+    # would overwrite an input before the GEMMs read it)
+    Bm = mat(k, n, 2 * FAKE)
+    C = mat(m, n, 3 * FAKE)
+    assert check(A, Bm, C, ws=FAKE + 7 * 2048, ws_bytes=res) == ALIAS        # inside A's last component
+    assert "workspace overlaps" in B.last_error()
+    assert check(A, Bm, C, ws=2 * FAKE - res + 8, ws_bytes=res) == ALIAS     # its end reaches B's first
+    assert check(A, Bm, C, ws=2 * FAKE - res, ws_bytes=res) == OK            # ends where B starts
+    # only the part of the workspace the plan uses counts: a larger buffer
+    # whose tail covers an input is fine when the resident plan ends before it
+    assert check(A, Bm, C, ws=2 * FAKE - res - 4096, ws_bytes=res + 8192) == OK
+    # the split form's digit buffers count too
+    rs, _ = B.workspace_size(m, n, k, 0xFF, 0xFF, "split_int8_crt", 0)
+    assert check(A, Bm, C, prec=4, ws=2 * FAKE - rs + 8, ws_bytes=rs) == ALIAS
 
 
 def test_workspace_sizes_and_errors():
@@ -146,9 +160,9 @@ def test_workspace_sizes_and_errors():
     assert ws_need(m, n, k, 0x01, 0x01) == (0, 0)
     assert ws_need(m, n, 0) == (0, 0)
     # split form: + digit buffers of one real product (rows padded to 128,
-    # columns to 64, k to 64; 2-byte BF16 digits, S = 7 by default)
+    # columns to 64, k to 64; 2-byte BF16 digits, S = 8 by default at k = 40)
     r_bf, m_bf = B.workspace_size(m, n, k, 0xFF, 0xFF, "split_bf16", 0)
-    dig = lambda rows: (7 * rows * 64 * 2 + 255) // 256 * 256 + (rows * 4 + 255) // 256 * 256
+    dig = lambda rows: (8 * rows * 64 * 2 + 255) // 256 * 256 + (rows * 4 + 255) // 256 * 256
     assert r_bf == res + dig(128) + dig(64) and m_bf == mn + dig(128) + dig(64)
     A, Bm, C = mat(m, k, FAKE), mat(k, n, 2 * FAKE), mat(m, n, 3 * FAKE)
     assert check(A, Bm, C, ws=4 * FAKE, ws_bytes=mn - 1) == WORKSPACE
@@ -238,3 +252,95 @@ def test_crt_limits():
         assert chk(k, slices=n_min) == OK
         if n_min > 1:
             assert chk(k, slices=n_min - 1) == INVALID
+
+
+@pytest.mark.parametrize("k", [1, 2, 40, 256, 257, 4096, 16384, 100000])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
+def test_default_slices_follow_k(kind, k):
+    """slices = 0 in a digit form resolves, from the call's k, to the fewest
+    slices whose digits carry 48 + ceil(log2(k) / 2) significand bits (the
+    oracle's restatement of the rule): the workspace of the default equals
+    that of the explicit count."""
+    from oracle import ozaki
+
+    prec = {"bf16": "split_bf16", "fp8": "split_fp8", "int8": "split_int8"}[kind]
+    S = ozaki.default_slices(kind, k)
+    assert ozaki.carried_bits(kind, S) >= 48 + ((k - 1).bit_length() + 1) // 2 or S == ozaki.MAX_SLICES[kind]
+    assert B.workspace_size(50, 30, k, 0xFF, 0xFF, prec, 0) == B.workspace_size(50, 30, k, 0xFF, 0xFF, prec, S)
+    if S > 1:
+        assert B.workspace_size(50, 30, k, 0xFF, 0xFF, prec, 0) != \
+            B.workspace_size(50, 30, k, 0xFF, 0xFF, prec, S - 1)
+
+
+def test_default_slices_at_the_benchmark_size():
+    """At k = 16384 the defaults carry 55 to 59 bits: BF16 8, FP8 12, INT8 8."""
+    from oracle import ozaki
+
+    assert [ozaki.default_slices(t, 16384) for t in ("bf16", "fp8", "int8")] == [8, 12, 8]
+    assert [ozaki.carried_bits(t, S) for t, S in (("bf16", 8), ("fp8", 12), ("int8", 8))] == [56, 59, 55]
+
+
+def test_variant_entry_points_take_the_gemm_arguments():
+    """bq_re_gemm, bq_cx_gemm and bq_rq_gemm share bq_gemm's argument
+    pattern (ops, precision, slices, workspace); argument errors come back
+    before any HIP call."""
+    lib = B.lib()
+    A, Bm, C = mat(4, 4, FAKE), mat(4, 4, 2 * FAKE), mat(4, 4, 3 * FAKE)
+    for name in ("bq_re_gemm", "bq_cx_gemm", "bq_rq_gemm"):
+        f = getattr(lib, name)
+        assert f(None, 1, 3, ctypes.byref(A), ctypes.byref(Bm), ctypes.byref(C), 4, 0, None, 0, None) == INVALID
+        assert "handle" in B.last_error()
+        h = ctypes.c_void_p(1)   # never dereferenced: validation fails first
+        assert f(h, 7, 0, ctypes.byref(A), ctypes.byref(Bm), ctypes.byref(C), 0, 0, None, 0, None) == INVALID
+        assert f(h, 0, 0, ctypes.byref(A), ctypes.byref(Bm), ctypes.byref(C), 9, 0, None, 0, None) == INVALID
+        assert f(h, 0, 0, None, ctypes.byref(Bm), ctypes.byref(C), 0, 0, None, 0, None) == INVALID
+
+
+def test_planner_log():
+    """BQ_LOG=1 prints one plan line per validated call on stderr."""
+    import subprocess
+    import sys
+
+    prog = f"""
+import ctypes, sys
+sys.path.insert(0, {ROOT!r})
+from paper_2609_02081_amd import _binding as B
+def mat(rows, cols, base, mask=0xFF):
+    M = B.BqMatrix()
+    for c in range(8):
+        M.comp[c] = (base + c * (1 << 20)) if (mask >> c & 1) else None
+    M.rows, M.cols, M.ld = rows, cols, cols
+    return M
+A, Bm, C = mat(40, 20, 1 << 40), mat(20, 30, 2 << 40), mat(40, 30, 3 << 40)
+res, mn = B.workspace_size(40, 30, 20)
+rc1 = B.lib().bq_gemm_check(1, 0, ctypes.byref(mat(20, 40, 1 << 40)), ctypes.byref(Bm), ctypes.byref(C), 0, 0,
+                            4 << 40, mn)
+rc2 = B.lib().bq_gemm_check(0, 0, ctypes.byref(mat(40, 20, 1 << 40, 0x0F)), ctypes.byref(mat(20, 30, 2 << 40, 0x0F)),
+                            ctypes.byref(C), 4, 0, 4 << 40, 1 << 30)
+print(rc1, rc2)
+"""
+    env = dict(os.environ, BQ_LOG="1")
+    r = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["0", "0"]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[bq] plan")]
+    assert len(lines) == 2, r.stderr
+    assert "m=40 n=30 k=20 op=TN" in lines[0] and "form=bilinear real_gemms=24" in lines[0]
+    assert "prec=fp64" in lines[0] and "workspace=streamed" in lines[0]
+    assert "maskA=0x0f" in lines[1] and "real_gemms=8" in lines[1] and "prec=split_int8_crt" in lines[1]
+    assert "slices=15" in lines[1] and "workspace=resident" in lines[1]
+    # off by default
+    env.pop("BQ_LOG")
+    r = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=120)
+    assert "[bq] plan" not in r.stderr
+
+
+def test_size_limits():
+    """Dimensions of 2^31 and more, or a matrix above 2^40 elements, are
+    refused before any size arithmetic could overflow."""
+    for m, n, k in ((1 << 31, 4, 4), (4, 4, 1 << 31), (1 << 21, 4, 1 << 20), (4, 1 << 30, 1 << 11)):
+        res, mn = ctypes.c_size_t(), ctypes.c_size_t()
+        assert B.lib().bq_gemm_workspace_size(m, n, k, 0xFF, 0xFF, 0, 0, ctypes.byref(res),
+                                              ctypes.byref(mn)) == UNSUPPORTED
+    assert B.lib().bq_gemm_workspace_size(1 << 20, 4, 1 << 20, 0xFF, 0xFF, 4, 0, None, None) == OK
+    assert check(mat(1 << 21, 8, FAKE), mat(8, 1 << 20, 2 * FAKE), mat(1 << 21, 1 << 20, 3 * FAKE)) == UNSUPPORTED

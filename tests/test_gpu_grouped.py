@@ -214,7 +214,7 @@ def test_512_products_log_uniform(bq):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "split_int8", "split_int8_crt"])
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp8", "split_int8", "split_int8_crt"])
 def test_split_batch(bq, prec):
     import torch
 

@@ -190,6 +190,67 @@ def test_variant_entry_points(bq):
     assert oracle.rel_frobenius(got, ref) <= TOL
 
 
+def test_variant_entry_points_ops_and_split(bq):
+    """The subalgebra entry points take bq_gemm's arguments: op T / H on
+    stored-transposed operands, and the split forms."""
+    import torch
+
+    rng = np.random.default_rng(55)
+    m, k, n = 70, 61, 53
+    At = inputs.blocks(rng, k, m, "normal")     # stored k x m: op T / H gives m x k
+    Bt = inputs.blocks(rng, n, k, "normal")     # stored n x k
+    a, b = dev(At), dev(Bt)
+    # real: op(A) = A^T, op(B) = B^T
+    c = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    bq.re_gemm(a[0], b[0], c, opA="T", opB="H")
+    torch.cuda.synchronize()
+    assert np.allclose(c.cpu().numpy(), At[0].T @ Bt[0].T, rtol=0, atol=1e-12)
+    # real quaternion, dagger of A and transpose of B, against the oracle's sign rules
+    Aq = At.copy(); Aq[4:] = 0
+    Bq = Bt.copy(); Bq[4:] = 0
+    cq = [torch.empty((m, n), dtype=torch.float64, device="cuda") for _ in range(4)]
+    bq.rq_gemm([a[i] for i in range(4)], [b[i] for i in range(4)], cq, opA="H", opB="T")
+    torch.cuda.synchronize()
+    ref = oracle.gemm(oracle.herm(Aq), oracle.transpose(Bq))
+    got = np.stack([x.cpu().numpy() for x in cq] + [np.zeros((m, n))] * 4)
+    assert np.all(ref[4:] == 0)
+    assert oracle.rel_frobenius(got, ref) <= TOL
+    # complex in the CRT form and in BF16 digits
+    A, B = inputs.pair(m, k, n, "uniform", seed=56)
+    a, b = dev(A), dev(B)
+    for prec in ("split_int8_crt", "split_bf16"):
+        cr = torch.empty((m, n), dtype=torch.float64, device="cuda"); ci = torch.empty_like(cr)
+        bq.cx_gemm((a[0], a[4]), (b[0], b[4]), (cr, ci), opA="C", prec=prec)
+        torch.cuda.synchronize()
+        refc = (A[0] - 1j * A[4]) @ (B[0] + 1j * B[4])
+        gotc = cr.cpu().numpy() + 1j * ci.cpu().numpy()
+        assert np.linalg.norm(gotc - refc) / np.linalg.norm(refc) <= TOL, prec
+
+
+def test_side_stream(bq):
+    """A call on a caller's stream (not torch's current one): the binding
+    allocates the output and workspace on that stream, so the caching
+    allocator reuses them only in its order; the result is the same."""
+    import torch
+
+    A, B = inputs.pair(300, 280, 260, "uniform", seed=57)
+    a, b = dev(A), dev(B)
+    ref = bq.bq_gemm(a, b)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    outs = []
+    for _ in range(4):
+        # each call's temporaries are freed when it returns; the next call on
+        # the same stream may take the same memory, in stream order
+        outs.append(bq.bq_gemm(a, b, stream=s))
+        junk = torch.empty(1 << 22, dtype=torch.float64, device="cuda")   # other work on the current stream
+        junk.fill_(float("nan"))
+    s.synchronize()
+    torch.cuda.synchronize()
+    for c in outs:
+        assert torch.equal(c, ref)
+
+
 def test_streamed_equals_resident(bq):
     A, B = inputs.pair(150, 140, 130, "uniform", seed=6)
     C1 = run(bq, A, B)

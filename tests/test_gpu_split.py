@@ -18,7 +18,6 @@ from paper_2609_02081_amd import inputs
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
 PRECS = {"bf16": "split_bf16", "fp8": "split_fp8", "int8": "split_int8"}
-DEFAULT_S = {"bf16": 7, "fp8": 13, "int8": 7}
 
 
 @pytest.fixture(scope="module")
@@ -50,16 +49,16 @@ def test_integer_bit_exact(bq, kind, S):
 
 
 @pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
-@pytest.mark.parametrize("kind,S", [("bf16", 3), ("bf16", 6), ("bf16", 8), ("fp8", 5), ("fp8", 9),
-                                    ("fp8", 13), ("int8", 4), ("int8", 7), ("int8", 9)])
+@pytest.mark.parametrize("kind,S", [("bf16", 3), ("bf16", 6), ("bf16", 8), ("fp8", 1), ("fp8", 5), ("fp8", 9),
+                                    ("fp8", 12), ("fp8", 13), ("int8", 4), ("int8", 7), ("int8", 9)])
 def test_matches_cpu_split_model(bq, kind, S, variant, monkeypatch):
-    """Every slice-GEMM block shape (the 8-wave one exists up to S = 6, or
-    S = 8 for FP8; the direct-to-LDS one for BF16 and INT8) against the CPU
-    split model; ragged shape."""
-    if variant == "0" and S > (8 if kind == "fp8" else 6):
+    """Every slice-GEMM block shape (the 8-wave one exists up to S = 6; BF16
+    and INT8 digits have five shapes, FP8 digits one) against the CPU split
+    model; ragged shape."""
+    if kind == "fp8" and variant != "0":
+        pytest.skip("FP8 digits have one block shape (the variant switch does not apply)")
+    if variant == "0" and kind != "fp8" and S > 6:
         pytest.skip("8-wave shape not built for this many slices")
-    if variant in ("3", "4") and kind == "fp8":
-        pytest.skip("direct-to-LDS shapes are built for 16-byte digit chunks (BF16, INT8)")
     if variant == "4" and S > 8:
         pytest.skip("the 32 x 32 shape is built up to 8 slices")
     monkeypatch.setenv("BQ_SLICE_VARIANT", variant)
@@ -77,7 +76,7 @@ def test_level_flush_interval(bq, kind, S, flush, variant, monkeypatch):
     """Level sums kept across k-steps and flushed every 1 or 3 k-steps (K =
     700: several flushes and a partial last interval) against the model."""
     if variant in ("3", "4") and kind == "fp8":
-        pytest.skip("direct-to-LDS shapes are built for BF16 and INT8")
+        pytest.skip("FP8 digits have one block shape (the variant switch does not apply)")
     monkeypatch.setenv("BQ_SLICE_VARIANT", variant)
     monkeypatch.setenv("BQ_SLICE_FLUSH", flush)
     A, B = inputs.pair(40, 700, 36, "logspread", seed=16)
@@ -162,4 +161,30 @@ def test_n8192_sampled(bq, kind, dist):
     Cs = C[:, ri][:, :, ci].cpu().numpy()
     err = oracle.rel_frobenius(Cs, oracle.gemm(As, Bs))
     print(f"split n=8192 {kind} {dist}: sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("kind", ["bf16", "int8", "fp8"])
+@pytest.mark.parametrize("dist", ["uniform", "logspread"])
+def test_n16384_default_slices_sampled(bq, kind, dist):
+    """The library's default slice count at the benchmark size (k = 16384:
+    BF16 8, FP8 12, INT8 8 slices) against the FP64 oracle on 40 x 40
+    sampled entries (the last row and column included), <= 1e-12."""
+    import torch
+
+    n, r = 16384, 40
+    print(f"split n=16384 {kind} {dist}: inputs", flush=True)
+    gen = inputs.device_uniform if dist == "uniform" else inputs.device_logspread
+    A = gen(n, n, 61, "cuda")
+    B = gen(n, n, 62, "cuda")
+    C = bq.bq_gemm(A, B, prec=PRECS[kind], slices=0)
+    torch.cuda.synchronize()
+    rows, cols = _sample(n, r, 63), _sample(n, r, 64)
+    ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+    As, Bs = A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy()
+    Cs = C[:, ri][:, :, ci].cpu().numpy()
+    del A, B, C
+    torch.cuda.empty_cache()
+    err = oracle.rel_frobenius(Cs, oracle.gemm(As, Bs))
+    print(f"split n=16384 {kind} {dist}: default slices, sampled rel err {err:.3e}", flush=True)
     assert err <= TOL

@@ -311,3 +311,82 @@ def test_faithful_restatement_passes_and_matches():
                                     "layout_swap_ij", "conj_field_unit"])
 def test_planted_mistakes(mutant):
     assert not _pins_hold(lambda A, B: _np_product(A, B, mutant))
+
+
+# --------------------------------------------------------------------------
+# The parity measure itself: every <= tolerance assertion goes through
+# oracle.rel_frobenius, so it is pinned to hand-computed values and shown to
+# reject the plausible ways of getting it wrong.
+# --------------------------------------------------------------------------
+def _rel_frobenius_pins_hold(fn) -> bool:
+    """Hand-computed cases of ||C - R||_F / ||R||_F over all 8 blocks jointly
+    (absolute error when R = 0)."""
+    R = np.zeros((8, 2, 2))
+    R[0] = 5.0                                   # ||R||_F^2 = 4 * 25 = 100
+    C = R.copy()
+    C[3, 0, 0] += 1.0                            # errors in two blocks that R leaves zero
+    C[6, 0, 1] -= 2.0                            # ||C - R||_F^2 = 1 + 4 = 5
+    cases = [(C, R, np.sqrt(5.0) / 10.0)]
+    # the error spread over every block: 8 blocks x 4 entries of 0.5 -> 32 * 0.25 = 8
+    R2 = np.full((8, 2, 2), 2.0)                 # ||R2||_F^2 = 32 * 4 = 128
+    cases.append((R2 + 0.5, R2, np.sqrt(8.0 / 128.0)))
+    # zero reference: the absolute error (3-4-5 across blocks 1 and 7)
+    Z = np.zeros((8, 1, 1))
+    E = Z.copy()
+    E[1] = 3.0
+    E[7] = -4.0
+    cases.append((E, Z, 5.0))
+    cases.append((R, R, 0.0))
+    for got, ref, want in cases:
+        v = fn(got, ref)
+        if not np.isclose(v, want, rtol=1e-15, atol=0.0):
+            return False
+    return True
+
+
+def test_rel_frobenius_pinned():
+    assert _rel_frobenius_pins_hold(oracle.rel_frobenius)
+    # the worked value, written out: sqrt(5) / 10
+    R = np.zeros((8, 2, 2)); R[0] = 5.0
+    C = R.copy(); C[3, 0, 0] = 1.0; C[6, 0, 1] = -2.0
+    assert oracle.rel_frobenius(C, R) == pytest.approx(0.22360679774997896, rel=1e-15)
+
+
+def _rf_no_sqrt(C, R):
+    d = float(np.sum((C - R) ** 2)); r = float(np.sum(R ** 2))
+    return d / r if r > 0 else d
+
+
+def _rf_per_block_mean(C, R):
+    vals = []
+    for c in range(8):
+        r = np.linalg.norm(R[c])
+        vals.append(np.linalg.norm(C[c] - R[c]) / r if r > 0 else np.linalg.norm(C[c] - R[c]))
+    return float(np.mean(vals))
+
+
+def _rf_first_block(C, R):
+    r = np.linalg.norm(R[0])
+    d = np.linalg.norm(C[0] - R[0])
+    return float(d / r) if r > 0 else float(d)
+
+
+def _rf_max_abs(C, R):
+    r = float(np.max(np.abs(R)))
+    d = float(np.max(np.abs(C - R)))
+    return d / r if r > 0 else d
+
+
+def _rf_relative_to_c(C, R):
+    r = float(np.sqrt(np.sum(C ** 2)))
+    d = float(np.sqrt(np.sum((C - R) ** 2)))
+    return d / r if r > 0 else d
+
+
+@pytest.mark.parametrize("mutant", [_rf_no_sqrt, _rf_per_block_mean, _rf_first_block, _rf_max_abs,
+                                    _rf_relative_to_c])
+def test_rel_frobenius_mutants_fail_the_pins(mutant):
+    """A dropped square root (1e-12 would become an effective 1e-6), per-block
+    norms, one block only, a max-abs norm, or the norm of the result instead
+    of the reference: each fails a pin."""
+    assert not _rel_frobenius_pins_hold(mutant)

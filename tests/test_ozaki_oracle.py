@@ -7,7 +7,7 @@ import pytest
 from oracle import ozaki
 from paper_2609_02081_amd import inputs
 
-KINDS = [("bf16", 8), ("fp8", 14), ("int8", 9)]
+KINDS = [("bf16", 8), ("fp8", 13), ("int8", 9)]
 
 
 @pytest.mark.parametrize("kind,S", KINDS)
@@ -50,6 +50,26 @@ def test_digit_bounds(kind, S):
     assert max(np.max(np.abs(q)) for q in Q) <= lim
 
 
+def test_fp8_digits_fit_e4m3():
+    """FP8 digits (beta 5, one bit of headroom) are integers in [-16, 16],
+    every one of which E4M3 (4 significant bits, exponent bias 7) holds
+    exactly; without the headroom the leading digit could reach 32, and 17
+    .. 31 are not E4M3 values."""
+    e4m3_ints = set()
+    for e in range(0, 9):                    # normal values 1.mmm x 2^e
+        for mant in range(8):
+            v = (8 + mant) * 2.0 ** (e - 3)
+            if v == int(v):
+                e4m3_ints.add(int(v))
+    assert set(range(0, 17)) <= e4m3_ints | {0} and 17 not in e4m3_ints and 31 not in e4m3_ints
+    X = np.array([[1.0 - 2.0 ** -12, 0.25, -0.7], [-0.75, 0.125, 0.5 - 2.0 ** -30]])
+    Q, _, _ = ozaki.digits(X, ozaki.BETA["fp8"], 6, 1, ozaki.HEAD["fp8"])
+    assert max(np.max(np.abs(q)) for q in Q) == 16
+    assert all(abs(int(v)) in e4m3_ints | {0} for q in Q for v in q.ravel())
+    Q0, _, _ = ozaki.digits(X, ozaki.BETA["fp8"], 2, 1, head=0)
+    assert np.max(np.abs(Q0[0])) == 32
+
+
 def test_int8_needs_headroom():
     """Without the headroom bit a leading INT8 digit of beta 7 can be 128,
     which a signed byte cannot hold; with it every digit fits."""
@@ -63,7 +83,8 @@ def test_int8_needs_headroom():
 @pytest.mark.parametrize("kind,S", [("bf16", 3), ("fp8", 5), ("int8", 3)])
 def test_integer_products_exact(kind, S):
     """Integers of at most 10 bits need 2 (bf16, int8) or 3 (fp8) digits;
-    with those pairs kept the split product is exact."""
+    with those pairs kept (S = 3 or 5: every pair of the needed digits has
+    s + t <= S + 1) the split product is exact."""
     rng = np.random.default_rng(7)
     X = rng.integers(-512, 513, size=(30, 70)).astype(np.float64)
     Y = rng.integers(-512, 513, size=(70, 20)).astype(np.float64)
