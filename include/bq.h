@@ -174,6 +174,25 @@ bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB,
                     bq_prec_t prec, int slices, void* ws, size_t ws_bytes,
                     bq_stream_t stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  bq_gemm
+ * with the workspace taken from a static device array of
+ * BQ_NOALLOC_SCRATCH_BYTES bytes that the library holds on each GPU it runs
+ * on until the process ends (its address is looked up once per device by
+ * bq_create); the call allocates nothing.  The resident plan runs when its
+ * workspace fits the array, else the streamed one; a product that needs
+ * more than the array returns BQ_ERR_WORKSPACE (nothing enqueued).  Square
+ * FP64 biquaternion products fit up to n = 1448 resident, n = 2896
+ * streamed.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, threads or handles) race, so the
+ * caller serialises them.  No part of the array has to start at zero (every
+ * kernel writes what it later reads), so nothing is cleared between calls.
+ * Other arguments, conventions and errors as for bq_gemm. */
+#define BQ_NOALLOC_SCRATCH_BYTES (256u << 20)
+bq_status_t bq_gemm_noalloc(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A,
+                            const bq_matrix_t* B, bq_matrix_t* C, bq_prec_t prec, int slices,
+                            bq_stream_t stream);
+
 /* Subalgebra special cases (Sec. III A: real, complex and real-quaternion
  * matrices embedded in H_C).  The arguments and conventions of bq_gemm (op
  * sign rules of Sec. III, precision, slices, workspace sized by

@@ -65,6 +65,8 @@ _SIGS = [
     ("bq_gemm", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int,
       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("bq_gemm_noalloc", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     ("bq_re_gemm", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _M, _M, _M, ctypes.c_int, ctypes.c_int,
       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -259,6 +261,21 @@ def bq_gemm(A, B, C=None, *, opA="N", opB="N", mask_a=FULL, mask_b=FULL, prec="f
     check(lib().bq_gemm(handle(dev.index or 0), OPS[opA], OPS[opB], ctypes.byref(Am), ctypes.byref(Bm),
                         ctypes.byref(Cm), PRECS[prec], slices, ctypes.c_void_p(workspace.data_ptr()),
                         ws_bytes, _stream(stream)))
+    return C
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def bq_gemm_noalloc(A, B, C, *, opA="N", opB="N", mask_a=FULL, mask_b=FULL, prec="fp64", slices=0, stream=None):
+    """C = op(A) op(B) into the caller's C (8, m, n), with the library's static
+    workspace: neither the library nor this function allocates device memory."""
+    Am = matrix(A, mask_a)
+    Bm = matrix(B, mask_b)
+    Cm = matrix(C)
+    dev = (C if _is_tensor(C) else next(t for t in C if t is not None)).device
+    check(lib().bq_gemm_noalloc(handle(dev.index or 0), OPS[opA], OPS[opB], ctypes.byref(Am), ctypes.byref(Bm),
+                                ctypes.byref(Cm), PRECS[prec], slices, _stream(stream)))
     return C
 
 

@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbq.so")
-SOURCES = ["bq_engine.cpp", "bq_kernels.hip", "bq_split.hip", "bq_split_f8.hip", "bq_crt.hip", "bq_heev.hip"]
+SOURCES = ["bq_engine.cpp", "bq_kernels.hip", "bq_split.hip", "bq_split_f8.hip", "bq_crt.hip", "bq_heev.hip",
+           "bq_noalloc.hip"]
 # The eigensolves of bq_heev call rocSOLVER (with rocBLAS for its handle).
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -31,6 +31,8 @@ struct bq_handle_s {
   bool trace = false;
   std::vector<TraceSlot> pending;
   rocblas_handle rb = nullptr;  // eigensolver calls; its device memory is always the caller's workspace
+  void* scratch = nullptr;      // this device's static workspace of bq_gemm_noalloc
+  size_t scratch_bytes = 0;
 };
 
 namespace {
@@ -1077,10 +1079,18 @@ bq_status_t bq_create(bq_handle_t* h, int device) {
     return hip_fail(e, "hipSetDevice");
   }
   const rocblas_status rs = rocblas_create_handle(&hh->rb);
+  // The static workspace of bq_gemm_noalloc: its device address on this
+  // device, looked up with the device current.
+  const hipError_t se = bq::noalloc_scratch(device, &hh->scratch, &hh->scratch_bytes);
   if (prev >= 0) (void)hipSetDevice(prev);
   if (rs != rocblas_status_success) {
     delete hh;
     return fail(BQ_ERR_HIP, "rocblas_create_handle failed");
+  }
+  if (se != hipSuccess) {
+    (void)rocblas_destroy_handle(hh->rb);
+    delete hh;
+    return hip_fail(se, "static workspace lookup");
   }
   *h = hh;
   return BQ_OK;
@@ -1182,6 +1192,17 @@ bq_status_t bq_gemm_check(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const 
 bq_status_t bq_gemm(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
                     bq_matrix_t* C, bq_prec_t prec, int slices, void* ws, size_t ws_bytes, bq_stream_t stream) {
   return run(h, opA, opB, A, B, C, prec, slices, ws, ws_bytes, 0xFFu, stream);
+}
+
+bq_status_t bq_gemm_noalloc(bq_handle_t h, bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_matrix_t* B,
+                            bq_matrix_t* C, bq_prec_t prec, int slices, bq_stream_t stream) {
+  if (!h) return fail(BQ_ERR_INVALID_VALUE, "handle is null");
+  if (!h->scratch) return fail(BQ_ERR_HIP, "no static workspace on this device");
+  const bq_status_t st = run(h, opA, opB, A, B, C, prec, slices, h->scratch, h->scratch_bytes, 0xFFu, stream);
+  if (st == BQ_ERR_WORKSPACE)
+    return fail(st, "bq_gemm_noalloc: " + g_detail + "; the static workspace holds " +
+                        std::to_string(h->scratch_bytes) + " B");
+  return st;
 }
 
 // The subalgebra entry points: bq_gemm with the inputs and the output

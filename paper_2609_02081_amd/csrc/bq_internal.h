@@ -177,6 +177,10 @@ struct TileConfig {
   int bm, bn, bk, wm, wn;
 };
 
+// Device address and size of this device's static workspace of
+// bq_gemm_noalloc (bq_noalloc.hip); looked up once per device.
+hipError_t noalloc_scratch(int device, void** ptr, size_t* bytes);
+
 // Launchers (bq_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_cgemm(int kind, const GemmArgs& g, int cfg, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, hipStream_t s);
