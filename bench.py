@@ -514,6 +514,207 @@ def host_cpu():
             "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
+def large_leg(bq, inputs, torch, n, log):
+    """One FP64 product at n (24576: the 2n x 2n complex isomorph exceeds
+    2^31 elements and one block 2^32 bytes) on the resident plan, the same
+    Hermitian workload as the headline: one warm-up, then the mean of two
+    timed products and the average GEMM launch from the library's trace."""
+    log(f"large leg: building Hermitian inputs n={n} on the device")
+    A, B = inputs.hermitian_pair(n, 3, "cuda")
+    C = torch.empty_like(A)
+    res, mn = bq.workspace_size(n, n, n)
+    ws = torch.empty(res, dtype=torch.uint8, device="cuda")
+    bq.bq_gemm(A, B, C, workspace=ws)
+    torch.cuda.synchronize()
+    bq.trace_enable(True)
+    bq.trace_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 2
+    e0.record()
+    for _ in range(reps):
+        bq.bq_gemm(A, B, C, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    recs = bq.trace_read()
+    bq.trace_enable(False)
+    ms = e0.elapsed_time(e1) / reps
+    gemm = [r for r in recs if r["kernel"] == "gemm_gauss"]
+    g_ms = sum(r["ms"] for r in gemm) / max(1, len(gemm))
+    g_tf = gemm[0]["flops"] / (g_ms * 1e-3) / 1e12 if gemm else None
+    out = {"workload": f"biquaternion GEMM n={n}, A Fock-like x B density-like Hermitian, FP64, resident plan "
+                       f"(complex isomorph 2n x 2n = {4 * n * n:.3e} elements > 2^31)",
+           "n": n, "ms": round(ms, 2), "eff_tflops": round(64 * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2),
+           "executed_tflops": round(24 * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2),
+           "gemm_avg_launch_ms": round(g_ms, 2), "gemm_tflops": round(g_tf, 2) if g_tf else None,
+           "gemm_frac_of_fp64_peak": round(g_tf / PEAK_FP64_TFLOPS, 4) if g_tf else None,
+           "workspace_GiB": round(res / 2 ** 30, 1), "A_B_C_GiB": round(3 * A.numel() * 8 / 2 ** 30, 1)}
+    log(f"large leg n={n}: {ms:.1f} ms, {out['eff_tflops']} effective TFLOP/s, GEMM {g_tf:.1f} TFLOP/s")
+    del A, B, C, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def config4_sweep(bq, inputs, torch, ns, log, r=96):
+    """The split forms' accuracy and speed per slice count (moduli for the
+    CRT form) at each n of ns, uniform[-1,1] and log-spread inputs: one
+    product per count, its time, the slice-GEMM rate from the library's
+    trace, and the relative Frobenius error of r x r sampled entries (the
+    last row and column included) against the oracle, beside the FP64 path
+    on the same inputs."""
+    import numpy as np
+
+    import oracle
+
+    counts = {"split_bf16": range(4, 9), "split_fp8": range(8, 14), "split_int8": range(6, 10),
+              "split_int8_crt": range(12, 17)}
+    rows_out = []
+    for n in ns:
+        for dist in ("uniform", "logspread"):
+            gen = inputs.device_uniform if dist == "uniform" else inputs.device_logspread
+            A = gen(n, n, 401, "cuda")
+            B = gen(n, n, 402, "cuda")
+            C = torch.empty_like(A)
+            rows, cols = sample_idx(n, r, 403), sample_idx(n, r, 404)
+            ri = torch.as_tensor(rows, device="cuda")
+            ci = torch.as_tensor(cols, device="cuda")
+            ref = oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy())
+
+            def one(prec, S):
+                res, _ = bq.workspace_size(n, n, n, prec=prec, slices=S)
+                ws = torch.empty(res, dtype=torch.uint8, device="cuda")
+                bq.bq_gemm(A, B, C, prec=prec, slices=S, workspace=ws)   # first call: any one-off cost
+                torch.cuda.synchronize()
+                bq.trace_enable(True)
+                bq.trace_read()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                bq.bq_gemm(A, B, C, prec=prec, slices=S, workspace=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                recs = bq.trace_read()
+                bq.trace_enable(False)
+                del ws
+                torch.cuda.empty_cache()
+                ms = e0.elapsed_time(e1)
+                sg = [x for x in recs if x["kernel"] in ("slice_gemm", "crt_gemm")]
+                sg_ms = sum(x["ms"] for x in sg)
+                err = oracle.rel_frobenius(C[:, ri][:, :, ci].cpu().numpy(), ref)
+                return ms, err, (sum(x["flops"] for x in sg) / (sg_ms * 1e-3) / 1e12 if sg_ms > 0 else None)
+
+            fp_ms, fp_err, _ = one("fp64", 0)
+            rows_out.append({"n": n, "dist": dist, "prec": "fp64", "slices": None, "ms": round(fp_ms, 1),
+                             "eff_tflops": round(64 * 2.0 * n ** 3 / (fp_ms * 1e-3) / 1e12, 1),
+                             "speed_vs_fp64": 1.0, "rel_err_vs_oracle": fp_err, "lowprec_tflops": None})
+            log(f"config4 n={n} {dist} fp64: {fp_ms:.1f} ms, err {fp_err:.2e}")
+            for prec, rng_ in counts.items():
+                for S in rng_:
+                    ms, err, lp = one(prec, S)
+                    rows_out.append({"n": n, "dist": dist, "prec": prec, "slices": S, "ms": round(ms, 1),
+                                     "eff_tflops": round(64 * 2.0 * n ** 3 / (ms * 1e-3) / 1e12, 1),
+                                     "speed_vs_fp64": round(fp_ms / ms, 3), "rel_err_vs_oracle": err,
+                                     "lowprec_tflops": round(lp, 1) if lp else None})
+                    log(f"config4 n={n} {dist} {prec} S={S}: {ms:.1f} ms, err {err:.2e}, "
+                        f"low-precision {lp:.0f} T/s")
+            del A, B, C
+            torch.cuda.empty_cache()
+    return {"workload": f"split forms per slice count, n in {list(ns)}, uniform[-1,1] and sign*10^U(-6,6) "
+                        f"(seeds 401, 402), error on {r} x {r} sampled entries vs the oracle",
+            "rows": rows_out}
+
+
+def power_probe(bq, inputs, torch, n, precs, seconds, log):
+    """Socket power and graphics clock while one form's products run back
+    to back for about `seconds` (n x n uniform inputs, library defaults), with
+    the rate of its dominant kernel from the library's trace: whether a
+    kernel runs below its nominal peak because the clock drops under load."""
+    A = inputs.device_uniform(n, n, 501, "cuda")
+    B = inputs.device_uniform(n, n, 502, "cuda")
+    C = torch.empty_like(A)
+    out = {"workload": f"n={n} uniform products back to back for about {seconds} s per form", "forms": {}}
+    kinds = {"fp64": ("gemm_gauss",), "split_int8_crt": ("crt_gemm",), "split_int8": ("slice_gemm",),
+             "split_fp8": ("slice_gemm",), "split_bf16": ("slice_gemm",)}
+    for prec in precs:
+        res, _ = bq.workspace_size(n, n, n, prec=prec)
+        ws = torch.empty(res, dtype=torch.uint8, device="cuda")
+        bq.bq_gemm(A, B, C, prec=prec, workspace=ws)
+        torch.cuda.synchronize()
+        bq.trace_enable(True)
+        bq.trace_read()
+        reps = 0
+        t0 = time.time()
+        with SmiSampler(interval=0.2) as smi:
+            while time.time() - t0 < seconds:
+                bq.bq_gemm(A, B, C, prec=prec, workspace=ws)
+                torch.cuda.synchronize()
+                reps += 1
+        wall = time.time() - t0
+        recs = bq.trace_read()
+        bq.trace_enable(False)
+        ks = [r for r in recs if r["kernel"] in kinds[prec]]
+        k_ms = sum(r["ms"] for r in ks)
+        rate = sum(r["flops"] for r in ks) / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
+        out["forms"][prec] = {"products": reps, "ms_per_product": round(wall * 1e3 / reps, 1),
+                              "kernel": kinds[prec][0], "kernel_rate_T_per_s": round(rate, 1) if rate else None,
+                              "kernel_share_of_time": round(k_ms / (wall * 1e3), 3), "power_clock": smi.summary()}
+        log(f"power probe {prec}: {reps} products, {rate:.0f} T/s, {smi.summary()}")
+        del ws
+        torch.cuda.empty_cache()
+    return out
+
+
+def summarize_config4(json_path, out_path, cmd):
+    """Markdown table of a --config4 run (the JSON line it printed)."""
+    with open(json_path) as f:
+        d = json.loads([l for l in f if l.startswith("{")][-1])["config4"]
+    lines = [f"# Split forms per slice count (config 4)", "",
+             f"Command: `{cmd}`", "", f"Workload: {d['workload']}.", "",
+             "| n | inputs | form | slices | ms | effective TFLOP/s | vs FP64 | rel. error vs oracle | "
+             "low-precision rate (T/s) |", "|---|---|---|---|---|---|---|---|---|"]
+    for r in d["rows"]:
+        lines.append(f"| {r['n']} | {r['dist']} | {r['prec']} | {r['slices'] if r['slices'] is not None else '-'} | "
+                     f"{r['ms']} | {r['eff_tflops']} | {r['speed_vs_fp64']} | {r['rel_err_vs_oracle']:.2e} | "
+                     f"{r['lowprec_tflops'] if r['lowprec_tflops'] is not None else '-'} |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def oracle_timings(log):
+    """The oracle timed in full on the host: n = 256 with one thread and with
+    all of them, and n = 4096 for the four subalgebras' inputs (the oracle
+    always forms all 64 real products; absent components are zero blocks)."""
+    import numpy as np
+
+    import oracle
+    from paper_2609_02081_amd import inputs
+
+    out = {"host": host_cpu(), "runs": []}
+    allt = oracle.num_threads()
+    A, B = inputs.pair(256, 256, 256, "uniform", seed=1)
+    for t in (1, allt):
+        oracle.set_num_threads(t)
+        t0 = time.perf_counter()
+        oracle.gemm(A, B)
+        dt = time.perf_counter() - t0
+        out["runs"].append({"n": 256, "mask": "biquaternion", "threads": t, "seconds": round(dt, 4),
+                            "eff_tflops": round(64 * 2.0 * 256 ** 3 / dt / 1e12, 5)})
+        log(f"oracle n=256, {t} threads: {dt:.3f} s")
+    oracle.set_num_threads(allt)
+    for name in ("biquaternion", "real_quaternion", "complex", "real"):
+        mask = inputs.MASKS[name]
+        A, B = inputs.pair(4096, 4096, 4096, "normal", seed=2, mask_a=mask, mask_b=mask)
+        t0 = time.perf_counter()
+        oracle.gemm(A, B)
+        dt = time.perf_counter() - t0
+        eff = {"biquaternion": 64, "real_quaternion": 16, "complex": 4, "real": 1}[name]
+        out["runs"].append({"n": 4096, "mask": name, "threads": allt, "seconds": round(dt, 2),
+                            "eff_tflops": round(eff * 2.0 * 4096 ** 3 / dt / 1e12, 5)})
+        log(f"oracle n=4096 {name}, {allt} threads: {dt:.1f} s")
+        del A, B
+    return out
+
+
 def sample_idx(n, r, seed):
     import numpy as np
 
@@ -546,6 +747,16 @@ def main():
                     help="split form the batch is repeated in (empty skips it)")
     ap.add_argument("--batched", type=int, default=512,
                     help="products in the batched leg (0 to skip)")
+    ap.add_argument("--large-n", type=int, default=24576,
+                    help="n of the FP64 leg beyond the 32-bit complex-isomorph limit (0 skips it)")
+    ap.add_argument("--config4", default="",
+                    help="only run the split forms' sweep over slice counts at these n (e.g. 8192,16384)")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="only time the oracle in full on the host (n = 256, 1 and all threads; n = 4096 x 4 masks)")
+    ap.add_argument("--power-probe", default="",
+                    help="only record power and clock while these forms run back to back (e.g. fp64,split_int8_crt)")
+    ap.add_argument("--summarize-config4", nargs=3, metavar=("JSON", "OUT_MD", "COMMAND"),
+                    help="markdown table of a --config4 run's JSON output")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates the HBM counters)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_TSV"),
@@ -556,11 +767,17 @@ def main():
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
         return
+    if args.summarize_config4:
+        summarize_config4(*args.summarize_config4)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, copy_bytes=args.copy_calibration or (1 << 32))
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.oracle_timings:
+        print(json.dumps({"oracle_timings": oracle_timings(log)}), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -578,6 +795,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     bq.lib()
+    if args.config4:
+        ns = [int(x) for x in args.config4.split(",") if x]
+        print(json.dumps({"config4": config4_sweep(bq, inputs, torch, ns, log)}), flush=True)
+        return
+    if args.power_probe:
+        precs = [x for x in args.power_probe.split(",") if x]
+        print(json.dumps({"power_probe": power_probe(bq, inputs, torch, n, precs, 12.0, log)}), flush=True)
+        return
     log(f"building Hermitian inputs n={n} on the device")
     t0 = time.time()
     A, B = inputs.hermitian_pair(n, args.seed, dev)
@@ -776,9 +1001,14 @@ def main():
     heev = None
     ops = None
     subalg = None
-    if args.batched > 0 or args.heev > 0 or args.ops_n > 0 or args.paper_n > 0 or args.subalg_n > 0:
+    large = None
+    if args.batched > 0 or args.heev > 0 or args.ops_n > 0 or args.paper_n > 0 or args.subalg_n > 0 or args.large_n > 0:
         del A, B, C
+        if not args.split:
+            del ws
         torch.cuda.empty_cache()
+    if args.large_n > 0:
+        large = large_leg(bq, inputs, torch, args.large_n, log)
     if args.ops_n > 0:
         ops = ops_leg(bq, inputs, torch, args.ops_n, log)
     if args.subalg_n > 0:
@@ -841,7 +1071,7 @@ def main():
            "rel_err_sampled_vs_oracle": rel_err,
            "roofline": roofline, "combine": combine, "cpu_baseline": cpu,
            "split_precision": split, "op_pairs": ops, "subalgebras": subalg, "batched": batched, "diagonalization": heev,
-           "slab_one_of_8": slab, "paper_like": paper_like}
+           "slab_one_of_8": slab, "large_n": large, "paper_like": paper_like}
     print(json.dumps(out), flush=True)
 
 

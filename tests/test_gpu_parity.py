@@ -340,15 +340,21 @@ def test_n4096_sampled(bq, name):
     assert oracle.rel_frobenius(Cs, oracle.iso_inv(ZA @ ZB)) <= TOL
 
 
-@pytest.mark.parametrize("n,streamed", [(16384, False), (24576, True)])
-def test_large_hermitian_sampled(bq, n, streamed):
+@pytest.mark.parametrize("n,streamed", [(16384, False), (24576, False), (24576, True)])
+def test_large_hermitian(bq, n, streamed):
     """n = 16384 and 24576 (the 2n x 2n complex isomorph has more than 2^31
-    elements at 24576, and one block is 4.8 GB > 2^32 bytes): Fock-like A
-    times density-like B, checked on sampled rows and columns that always
-    include the last ones (largest offsets)."""
+    elements at 24576, and one block is 4.8 GB > 2^32 bytes), resident and
+    streamed plans: Fock-like A times density-like B, checked on sampled rows
+    and columns that always include the last ones (largest offsets), and for
+    the resident plans on every entry of C at once by a Gaussian probe: for a
+    biquaternion X (n x p) with N(0,1) entries, E ||(C - AB) X||^2 is
+    proportional to ||C - AB||_F^2 with the same constant as E ||AB X||^2 to
+    ||AB||_F^2, so rho = ||C X - A (B X)||_F / ||A (B X)||_F estimates the
+    relative Frobenius error.  C X, B X and A (B X) are the oracle's
+    products, taken in row slabs of the device matrices."""
     import torch
 
-    print(f"n={n}: building Hermitian inputs on the device", flush=True)
+    print(f"n={n} streamed={streamed}: building Hermitian inputs on the device", flush=True)
     A, B = inputs.hermitian_pair(n, 3, "cuda")
     C = bq.bq_gemm(A, B, streamed=streamed)
     torch.cuda.synchronize()
@@ -359,40 +365,26 @@ def test_large_hermitian_sampled(bq, n, streamed):
     As = A[:, ri, :].cpu().numpy()
     Bs = B[:, :, ci].cpu().numpy()
     Cs = C[:, ri][:, :, ci].cpu().numpy()
-    del A, B, C
-    torch.cuda.empty_cache()
     err = oracle.rel_frobenius(Cs, oracle.gemm(As, Bs))
     print(f"n={n}: sampled rel err {err:.3e}", flush=True)
     assert err <= TOL
+    if not streamed:
+        p, slab = 4, 1024
+        X = inputs.blocks(np.random.default_rng(61), n, p, "normal")
 
+        def apply(M, Y):
+            out = np.empty((8, n, Y.shape[2]))
+            for r0 in range(0, n, slab):
+                out[:, r0:r0 + slab] = oracle.gemm(M[:, r0:r0 + slab].cpu().numpy(), Y)
+            return out
 
-def test_large_gaussian_probe(bq):
-    """Whole-matrix check at n = 16384 (every entry of C, not a sample): for a
-    biquaternion X (n x p) with N(0,1) entries, E ||(C - AB) X||^2 is
-    proportional to ||C - AB||_F^2 with the same constant as E ||AB X||^2 to
-    ||AB||_F^2, so rho = ||C X - A (B X)||_F / ||A (B X)||_F estimates the
-    relative Frobenius error.  C X, B X and A (B X) are the oracle's products,
-    taken in row slabs of the device matrices."""
-    import torch
-
-    n, p, slab = 16384, 4, 1024
-    print(f"n={n}: Gaussian probe, building Hermitian inputs on the device", flush=True)
-    A, B = inputs.hermitian_pair(n, 3, "cuda")
-    C = bq.bq_gemm(A, B)
-    torch.cuda.synchronize()
-    X = inputs.blocks(np.random.default_rng(61), n, p, "normal")
-
-    def apply(M, Y):
-        out = np.empty((8, n, Y.shape[2]))
-        for r0 in range(0, n, slab):
-            out[:, r0:r0 + slab] = oracle.gemm(M[:, r0:r0 + slab].cpu().numpy(), Y)
-        return out
-
-    CX = apply(C, X)
-    ABX = apply(A, apply(B, X))
-    rho = oracle.rel_frobenius(CX, ABX)
-    print(f"n={n}: Gaussian-probe relative error estimate {rho:.3e}", flush=True)
-    assert rho <= TOL
+        CX = apply(C, X)
+        ABX = apply(A, apply(B, X))
+        rho = oracle.rel_frobenius(CX, ABX)
+        print(f"n={n}: Gaussian-probe relative error estimate {rho:.3e}", flush=True)
+        assert rho <= TOL
+    del A, B, C
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("mask", [0xFF, 0x01])
