@@ -222,7 +222,11 @@ int bq_plan_real_gemms(unsigned maskA, unsigned maskB);
  * launch for every problem, then persistent launches whose blocks take
  * (problem, 64 x 64 tile) work items, largest problems first: either one
  * launch whose items run the problem's eight complex products on their tile
- * in turn, or one launch per complex product (the autotuner picks).  CRT
+ * in turn, or one launch per complex product (the autotuner picks); in the
+ * latter the Hadamard products P5..P8 go first and write their P into the
+ * problem's workspace, one launch forms their Hadamard sums, and the direct
+ * products P1..P4 write each C block once (FP64 workspace per problem: the
+ * pre-combined operands plus 8 blocks of m x round_up(n, 8) doubles).  CRT
  * form: per complex product, one launch for each stage over every problem
  * (exponents, residues, residue GEMMs, reconstruction; stages split by
  * modulus count where that differs); each problem keeps its own workspace

@@ -90,7 +90,7 @@ __device__ __forceinline__ void crt_split_left_at(const SplitArgs& a, const int*
     const double x = (r < a.rows && c < a.cols) ? operand_value(a, r * a.ld + c) : 0.0;
     crt_residues<N>(x, e, a.beta, q[t]);
   }
-  const int64_t o = digit_offset(1, r, kk, a.kp);
+  const int64_t o = digit_offset(r, kk, a.kp);
 #pragma unroll
   for (int i = 0; i < N; ++i)
     *reinterpret_cast<unsigned short*>(static_cast<unsigned char*>(out) + (int64_t)i * a.slice_stride + o) =
@@ -124,7 +124,7 @@ __device__ __forceinline__ void crt_split_right_block(const SplitArgs& a, const 
 #pragma unroll
     for (int i = 0; i < N; ++i) q[i][t >> 2] |= (int)(unsigned char)d[i] << (8 * (t & 3));
   }
-  const int64_t o = digit_offset(1, c, k0, a.kp);
+  const int64_t o = digit_offset(c, k0, a.kp);
 #pragma unroll
   for (int i = 0; i < N; ++i)
     *reinterpret_cast<i4v*>(static_cast<unsigned char*>(out) + (int64_t)i * a.slice_stride + o) = q[i];

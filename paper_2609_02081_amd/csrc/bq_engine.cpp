@@ -539,7 +539,6 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
   return BQ_OK;
 }
 
-// Tile order (BQ_TILE_ORDER="xcd,group_m" overrides the default "1,8").
 // Tile order of the single-call GEMM: each XCD takes a contiguous range of
 // tiles, walked in groups of 4 tile rows (groups of 2, 4 and 8 tie at
 // n = 16384; at n = 22000 4 is 2 % faster than 8).  BQ_TILE_ORDER="xcd,group"
@@ -554,14 +553,6 @@ void tile_order(int* xcd, int* group) {
     *xcd = a != 0;
     *group = b;
   }
-}
-
-// Slice-GEMM block shape (BQ_SLICE_VARIANT = 0 .. 4 overrides the default).
-int slice_variant() {
-  const char* e = std::getenv("BQ_SLICE_VARIANT");
-  if (!e || !*e) return -1;
-  const int v = std::atoi(e);
-  return (v >= 0 && v <= 4) ? v : -1;
 }
 
 // BQ_SLICE_FLUSH = f > 0 flushes the level sums at least every f k-steps
@@ -708,20 +699,18 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       ++sg.ntgt;
     }
     if (sg.ntgt == 0) return hipSuccess;
-    const int variant = bq::resolve_slice_variant(pr.et, S, slice_variant());
-    const int tiled = bq::slice_variant_tiled(variant);
     // The left factor takes one exponent per row of op(A): along the stored
     // rows (row kernels) for N and C, along the stored columns (column
     // kernels, which also transpose the digits) for T and H; the right factor
     // the other way round.
     bq::SplitArgs xa = pl.ta ? bq::SplitArgs{x1, x2, xw1, xw2, ldx, k, m, 0, sl.rows_pad, sl.kp,
-                                             sl.rows_pad * sl.kp, beta, head, 0, tiled}
+                                             sl.rows_pad * sl.kp, beta, head, 0}
                              : bq::SplitArgs{x1, x2, xw1, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp,
-                                             sl.rows_pad * sl.kp, beta, head, 1, tiled};
+                                             sl.rows_pad * sl.kp, beta, head, 1};
     bq::SplitArgs ya = pl.tb ? bq::SplitArgs{y1, y2, yw1, yw2, ldy, n, k, sl.cols_pad, 0, sl.kp,
-                                             sl.cols_pad * sl.kp, beta, head, 1, tiled}
+                                             sl.cols_pad * sl.kp, beta, head, 1}
                              : bq::SplitArgs{y1, y2, yw1, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp,
-                                             sl.cols_pad * sl.kp, beta, head, 0, tiled};
+                                             sl.cols_pad * sl.kp, beta, head, 0};
     const double elems_x = double(m) * double(k), elems_y = double(k) * double(n);
     {
       Tracer tr(h, s, BQ_KERNEL_SPLIT, -1, m, k, 0, 0.0,
@@ -751,7 +740,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
     sg.ldc = C->ld;
     const double pairs = double(S) * double(S + 1) / 2.0;
     Tracer tr(h, s, BQ_KERNEL_SLICE_GEMM, S, m, n, k, pairs * 2.0 * double(m) * double(n) * double(k), 0.0);
-    hipError_t e = bq::launch_slice_gemm(pr.et, S, variant, sg, s);
+    hipError_t e = bq::launch_slice_gemm(pr.et, S, sg, s);
     tr.done();
     return e;
   };
@@ -763,13 +752,13 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
   auto crt_product = [&](const double* x1, const double* x2, double xw2, int64_t ldx, const double* y1,
                          const double* y2, double yw2, int64_t ldy, int q) -> hipError_t {
     bq::SplitArgs xa = pl.ta ? bq::SplitArgs{x1, x2, 1.0, xw2, ldx, k, m, 0, sl.rows_pad, sl.kp,
-                                             sl.rows_pad * sl.kp, beta, 0, 0, 1}
+                                             sl.rows_pad * sl.kp, beta, 0, 0}
                              : bq::SplitArgs{x1, x2, 1.0, xw2, ldx, m, k, sl.rows_pad, 0, sl.kp,
-                                             sl.rows_pad * sl.kp, beta, 0, 1, 1};
+                                             sl.rows_pad * sl.kp, beta, 0, 1};
     bq::SplitArgs ya = pl.tb ? bq::SplitArgs{y1, y2, 1.0, yw2, ldy, n, k, sl.cols_pad, 0, sl.kp,
-                                             sl.cols_pad * sl.kp, beta, 0, 1, 1}
+                                             sl.cols_pad * sl.kp, beta, 0, 1}
                              : bq::SplitArgs{y1, y2, 1.0, yw2, ldy, k, n, 0, sl.cols_pad, sl.kp,
-                                             sl.cols_pad * sl.kp, beta, 0, 0, 1};
+                                             sl.cols_pad * sl.kp, beta, 0, 0};
     if (rec) {
       const int dq = sl.digit_sets > 1 ? q : 0;
       rec->splits.push_back({{xa, crt_ea[q], crt_da[dq]}, S, round});
@@ -1251,6 +1240,8 @@ struct bq_grouped_plan_s {
   int* d_counter = nullptr;
   bq::CombineArgs* d_comb = nullptr;
   int64_t* d_prefix = nullptr;
+  bq::CombineArgs* d_ht = nullptr;  // per-product schedule: Hadamard sums of P5..P8, one per problem
+  int64_t* d_ht_prefix = nullptr;
   int nitems = 0;
   int ncomb = 0;
   int64_t total_rows = 0;
@@ -1270,7 +1261,7 @@ struct bq_grouped_plan_s {
 
 namespace {
 
-constexpr int kGroupedTile = 64;  // both grouped tile configurations are 64 x 64
+constexpr int kGroupedTile = 64;  // every grouped tile configuration is 64 x 64
 
 void grouped_release_graph(bq_grouped_plan_t p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -1454,10 +1445,18 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
       st = execute(p->h, p->plans[p->order[i]], p->pr, &q.A, &q.B, &q.C, 0xFFu, ws, false, p->cap);
     }
   } else {
-    std::vector<bq::CombineArgs> comb;
-    std::vector<int64_t> prefix;
+    // One launch per complex product (schedule bit 2): the Hadamard
+    // products P5..P8 go first and write their P into the problem's
+    // workspace, one pass forms the Hadamard sums S_w = sum_q H[w][q] P_{5+q}
+    // in place (the 4 x 4 combination of the pre-combination kernel), and
+    // the direct products P1..P4 write C_w = c_w P_w + s_w S_w once: C is
+    // never read, against four read-modify-writes of all eight C blocks
+    // when each Hadamard product adds into C.
+    const bool defer = (p->dyn & 2) != 0;
+    std::vector<bq::CombineArgs> comb, ht;
+    std::vector<int64_t> prefix, ht_prefix;
     std::vector<bq::GemmArgs> prods(size_t(p->count) * 8);
-    int64_t rows = 0;
+    int64_t rows = 0, ht_rows = 0;
     for (int pi = 0; pi < p->count; ++pi) {
       const bq_problem_t& q = p->probs[pi];
       const Plan& pl = p->plans[pi];
@@ -1490,10 +1489,51 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
         rows += ca.rows;
         comb.push_back(ca);
       }
+      // Hadamard products' P (deferred schedule): 4 complex blocks after the
+      // pre-combined operands, rows of npad doubles.
+      const size_t p1 = align256(size_t(m) * size_t(npad) * 8);
+      double *Pr[4], *Pi[4];
+      for (int c = 0; c < 4; ++c) {
+        Pr[c] = reinterpret_cast<double*>(wp); wp += p1;
+        Pi[c] = reinterpret_cast<double*>(wp); wp += p1;
+      }
+      // A problem defers its Hadamard sums when it runs all eight complex
+      // products of the bilinear form: P1..P4 in slots 0..3, P5..P8 in 4..7.
+      const int np = int(pl.prods.size());
+      bool full = defer && pl.bilinear && np == 8;
+      for (int j = 0; full && j < 8; ++j) full = pl.prods[j].L.combo == (j < 4 ? -1 : j - 4);
+      double had_coef[4] = {0.0, 0.0, 0.0, 0.0};  // s_w: C_w gets s_w S_w
+      if (full) {
+        bq::CombineArgs h{};
+        for (int u = 0; u < 4; ++u) {
+          h.src[u] = Pr[u];
+          h.src[u + 4] = Pi[u];
+          h.dst_r[u] = Pr[u];
+          h.dst_i[u] = Pi[u];
+          for (int w = 0; w < 4; ++w) h.w[w][u] = kHad[w][u];
+        }
+        h.lds = h.ldd = npad;
+        h.rows = m;
+        h.cols = n;
+        h.nq = 4;
+        ht_prefix.push_back(ht_rows);
+        ht_rows += m;
+        ht.push_back(h);
+        for (int j = 4; j < 8; ++j)
+          for (const Tgt& t : pl.prods[j].tgts) had_coef[t.w] = t.coef.re / kHad[t.w][j - 4];
+      }
+      // Slots in launch order: with one launch per slot, slots 4..7 run
+      // first; WRITE / ACCUM of each C block follow that order.
+      static constexpr int kSeq[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+      static constexpr int kDeferSeq[8] = {4, 5, 6, 7, 0, 1, 2, 3};
+      const int* seq = defer ? kDeferSeq : kSeq;
       bool touched[8] = {};
-      int qi = 0;
-      for (const Prod& pd : pl.prods) {
+      for (int si = 0; si < 8; ++si) {
+        const int qi = seq[si];
+        if (qi >= np) continue;
+        const Prod& pd = pl.prods[qi];
         Operand L = pd.L, R = pd.R;
+        const int combo = L.combo;
         if (L.combo >= 0) {
           L.r = cAr[L.combo]; L.i = cAi[L.combo]; L.ld = pl.ta ? mpad : kpad;
           R.r = cBr[R.combo]; R.i = cBi[R.combo]; R.ld = pl.tb ? kpad : npad;
@@ -1505,22 +1545,39 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
         g.ta = pl.ta; g.tb = pl.tb;
         g.sL = L.s; g.sR = R.s;
         g.ldc = q.C.ld;
+        g.ldadd = npad;
         g.xcd_remap = 0;
         g.group_m = 1;
         auto al16 = [](const double* x) { return (reinterpret_cast<uintptr_t>(x) & 15u) == 0; };
         g.vec = (g.lda % 2 == 0) && (g.ldb % 2 == 0) && al16(g.lr) && al16(g.li) && al16(g.rr) && al16(g.ri);
-        for (const Tgt& t : pd.tgts) {
+        if (full && combo >= 0) {
+          // P of a Hadamard product into the workspace, written once.
           bq::Target T{};
-          T.ar = t.coef.re;
-          T.ai = t.coef.im;
-          T.cr = q.C.comp[t.w];
-          T.ci = q.C.comp[t.w + 4];
-          T.mode_r = touched[t.w] ? bq::TGT_ACCUM : bq::TGT_WRITE;
-          T.mode_i = touched[t.w + 4] ? bq::TGT_ACCUM : bq::TGT_WRITE;
-          touched[t.w] = touched[t.w + 4] = true;
+          T.ar = 1.0;
+          T.cr = Pr[combo];
+          T.ci = Pi[combo];
+          T.mode_r = T.mode_i = bq::TGT_WRITE;
           g.tgt[g.ntgt++] = T;
+          g.ldc = npad;
+        } else {
+          for (const Tgt& t : pd.tgts) {
+            bq::Target T{};
+            T.ar = t.coef.re;
+            T.ai = t.coef.im;
+            T.cr = q.C.comp[t.w];
+            T.ci = q.C.comp[t.w + 4];
+            T.mode_r = touched[t.w] ? bq::TGT_ACCUM : bq::TGT_WRITE;
+            T.mode_i = touched[t.w + 4] ? bq::TGT_ACCUM : bq::TGT_WRITE;
+            touched[t.w] = touched[t.w + 4] = true;
+            if (full) {  // direct product: the only writer of C_w, plus s_w S_w
+              T.sr = Pr[t.w];
+              T.si = Pi[t.w];
+              T.sc = had_coef[t.w];
+            }
+            g.tgt[g.ntgt++] = T;
+          }
         }
-        prods[size_t(pi) * 8 + qi++] = g;
+        prods[size_t(pi) * 8 + qi] = g;
       }
     }
     // Tables go to the device before recording (a synchronous copy may not
@@ -1530,15 +1587,24 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
       e = hipMemcpy(p->d_comb, comb.data(), comb.size() * sizeof(bq::CombineArgs), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(p->d_prefix, prefix.data(), prefix.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !ht.empty())
+      e = hipMemcpy(p->d_ht, ht.data(), ht.size() * sizeof(bq::CombineArgs), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !ht.empty())
+      e = hipMemcpy(p->d_ht_prefix, ht_prefix.data(), ht_prefix.size() * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "grouped table upload");
     e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     e = bq::launch_grouped_combine(p->d_comb, p->d_prefix, p->ncomb, rows, p->cap);
-    if (p->dyn & 2) {
-      for (int q = 0; q < 8 && e == hipSuccess; ++q)
-        if (p->round_n[q] > 0)
+    if (defer) {
+      // Hadamard products (rounds 4..7), their sums, then the direct products.
+      auto round = [&](int q) {
+        if (e == hipSuccess && p->round_n[q] > 0)
           e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, p->d_prods, p->d_items + p->nitems + p->round_off[q],
                                  p->round_n[q], p->d_counter, p->blocks, p->cap);
+      };
+      for (int q = 4; q < 8; ++q) round(q);
+      if (e == hipSuccess) e = bq::launch_grouped_combine(p->d_ht, p->d_ht_prefix, int(ht.size()), ht_rows, p->cap);
+      for (int q = 0; q < 4; ++q) round(q);
     } else if (e == hipSuccess) {
       e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, p->d_prods, p->d_items, p->nitems, p->d_counter,
                              p->blocks, p->cap);
@@ -1615,6 +1681,7 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
     }
     size_t res = 0, mn = 0;
     workspace_need(pl, pr, m, n, k, &res, &mn, pr.et == 3);
+    if (pr.et < 0) res += 8 * align256(size_t(m) * size_t(round_up(n, 8)) * 8);  // the Hadamard products' P
     if (pr.et < 0 || pr.et == 3) {
       offs[i] = total_ws;
       total_ws += res;
@@ -1723,6 +1790,8 @@ bq_status_t bq_grouped_plan_create(bq_handle_t h, int count, const bq_problem_t*
     if (e == hipSuccess) e = hipMalloc(&p->d_counter, 256);
     if (e == hipSuccess) e = hipMalloc(&p->d_comb, sizeof(bq::CombineArgs) * size_t(p->ncomb));
     if (e == hipSuccess) e = hipMalloc(&p->d_prefix, sizeof(int64_t) * size_t(p->ncomb));
+    if (e == hipSuccess) e = hipMalloc(&p->d_ht, sizeof(bq::CombineArgs) * size_t(count));
+    if (e == hipSuccess) e = hipMalloc(&p->d_ht_prefix, sizeof(int64_t) * size_t(count));
     if (e == hipSuccess)
       e = hipMemcpy(p->d_items, items.data(), sizeof(bq::GroupedItem) * items.size(), hipMemcpyHostToDevice);
   }
@@ -1845,6 +1914,8 @@ bq_status_t bq_grouped_plan_destroy(bq_grouped_plan_t plan) {
   if (plan->d_counter) (void)hipFree(plan->d_counter);
   if (plan->d_comb) (void)hipFree(plan->d_comb);
   if (plan->d_prefix) (void)hipFree(plan->d_prefix);
+  if (plan->d_ht) (void)hipFree(plan->d_ht);
+  if (plan->d_ht_prefix) (void)hipFree(plan->d_ht_prefix);
   if (plan->d_crt) (void)hipFree(plan->d_crt);
   delete plan;
   return BQ_OK;

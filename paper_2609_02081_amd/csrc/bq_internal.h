@@ -20,13 +20,19 @@ enum Kind : int { KIND_GAUSS = 0, KIND_RC = 1, KIND_CR = 2, KIND_RR = 3 };
 enum TargetMode : int { TGT_SKIP = 0, TGT_WRITE = 1, TGT_ACCUM = 2 };
 
 // One output quaternion unit w receives coef * P:
-//   C_w     (=cr)  op=  ar * P_R - ai * P_I
-//   C_{w+4} (=ci)  op=  ar * P_I + ai * P_R
+//   C_w     (=cr)  op=  ar * P_R - ai * P_I  [+ sc * sr]
+//   C_{w+4} (=ci)  op=  ar * P_I + ai * P_R  [+ sc * si]
+// sr, si (may be null): an addend block pair with leading dimension
+// GemmArgs::ldadd (the batched form's Hadamard sums, added by the direct
+// products' epilogue so that C is written once and never read).
 struct Target {
   double* cr;
   double* ci;
   double ar, ai;
   int mode_r, mode_i;
+  const double* sr;
+  const double* si;
+  double sc;
 };
 
 constexpr int kMaxTargets = 4;
@@ -47,6 +53,7 @@ struct GemmArgs {
   int xcd_remap;  // 1: deal contiguous tile ranges to the 8 XCDs
   int group_m;    // tile-rows per group of the grouped tile order (>= 1)
   int ta, tb;     // 1: lr/li stored k x m (lda along m), rr/ri stored n x k (ldb along k)
+  int64_t ldadd;  // leading dimension of the targets' addend blocks
 };
 
 // Linear combinations of quaternion components (the Hadamard rows of
@@ -82,7 +89,6 @@ struct SplitArgs {
   int beta;                    // digit width in bits
   int head;                    // exponent headroom: row/column exponent = frexp exponent + head
   int left;
-  int tiled;                   // digit layout: 0 = D[s][row][kk]; 1, 2 = 64-row x one-k-step tiles of 64- or 32-byte rows
 };
 
 constexpr int kMaxSliceTargets = 8;
@@ -202,13 +208,11 @@ hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_pr
 hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out, hipStream_t s);
 // Row (a.left) or column exponents of a split operand into exps.
 hipError_t launch_split_exponents(const SplitArgs& a, int* exps, hipStream_t s);
-hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t s);  // variant -1: default
+hipError_t launch_slice_gemm(int et, int S, const SliceGemmArgs& g, hipStream_t s);
 // FP8 digits (bq_split_f8.hip): beta 5, headroom 1, 1..13 slices.
 hipError_t launch_slice_gemm_f8(int S, const SliceGemmArgs& g, hipStream_t s);
 int f8_beta();
 int f8_head();
-int resolve_slice_variant(int et, int S, int variant);  // the shape launch_slice_gemm runs
-int slice_variant_tiled(int variant);                    // digit layout the shape reads (SplitArgs::tiled)
 int max_slices(int et);
 int slice_block_rows(int et, int S);  // rows of a slice-GEMM block tile (128 or 64)
 int slice_kstep(int et);              // k per MFMA step (32 or 64)

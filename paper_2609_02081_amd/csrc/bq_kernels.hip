@@ -115,7 +115,9 @@ __device__ __forceinline__ void load_pairs(double (&dst)[2 * PAIRS], const doubl
 // DEEP: two register sets, global loads two k-steps ahead and the LDS store
 // of the next stage three quarters of the way through the current k-step's
 // MFMAs (32 more registers; used where they fit without spills).
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0, int DEEP = 0>
+// ADD: targets may carry an addend matrix (Target::sr / si, scaled by sc,
+// leading dimension GemmArgs::ldadd); only the batched kernel uses it.
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0, int DEEP = 0, int ADD = 0>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
                                           TileSmem<KIND, BM, BN, BK>& sm) {
   constexpr int NWN = BN / WN;
@@ -337,6 +339,25 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   const int ntgt = g.ntgt;
   for (int t = 0; t < ntgt; ++t) {
     const Target T = g.tgt[t];
+    // Addends (ADD): every value of the wave tile is loaded before the first
+    // store, so the loads are in flight together rather than one per store.
+    constexpr int AM = ADD ? MI : 1, AN = ADD ? NI : 1;
+    double add_r[AM][AN][4], add_i[AM][AN][4];
+    if constexpr (ADD) {
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = wm0 + i * 16 + fk + 4 * v;
+            const int64_t c = wn0 + j * 16 + fr;
+            const bool in = r < mrem && c < nrem;
+            const int64_t aoff = (m0 + r) * g.ldadd + n0 + c;
+            add_r[i][j][v] = (in && T.sr) ? T.sr[aoff] : 0.0;
+            add_i[i][j][v] = (in && T.si) ? T.si[aoff] : 0.0;
+          }
+    }
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -366,11 +387,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
           const int64_t off = (m0 + r) * ldc + n0 + c;
           if (T.mode_r != TGT_SKIP) {
             double val = (T.ai == 0.0) ? T.ar * pr : ((T.ar == 0.0) ? -T.ai * pi : T.ar * pr - T.ai * pi);
+            if (ADD && T.sr) val = __builtin_fma(T.sc, add_r[ADD ? i : 0][ADD ? j : 0][v], val);
             if (T.mode_r == TGT_ACCUM) val += T.cr[off];
             T.cr[off] = val;
           }
           if (T.mode_i != TGT_SKIP) {
             double val = (T.ai == 0.0) ? T.ar * pi : ((T.ar == 0.0) ? T.ai * pr : T.ar * pi + T.ai * pr);
+            if (ADD && T.si) val = __builtin_fma(T.sc, add_i[ADD ? i : 0][ADD ? j : 0][v], val);
             if (T.mode_i == TGT_ACCUM) val += T.ci[off];
             T.ci[off] = val;
           }
@@ -546,13 +569,13 @@ grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* c
       const int64_t m0 = (int64_t)w.tm * BM, n0 = (int64_t)w.tn * BN;
       // op T / H operands are read in their stored orientation
       if constexpr (OPS >= 0) {
-        gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, (OPS >> 1), (OPS & 1)>(g, m0, n0, sm);
+        gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, (OPS >> 1), (OPS & 1), 0, 1>(g, m0, n0, sm);
       } else if (g.ta) {
-        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 1>(g, m0, n0, sm);
-        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 0>(g, m0, n0, sm);
+        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 1, 0, 1>(g, m0, n0, sm);
+        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 0, 0, 1>(g, m0, n0, sm);
       } else {
-        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 1>(g, m0, n0, sm);
-        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 0>(g, m0, n0, sm);
+        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 1, 0, 1>(g, m0, n0, sm);
+        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 0, 0, 1>(g, m0, n0, sm);
       }
     }
     if (!DYN) it += gridDim.x;
@@ -564,8 +587,8 @@ grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* c
 // ---------------------------------------------------------------------------
 static const TileConfig kConfigs[] = {
     {64, 64, 16, 32, 32},    // 0: 4 waves, 2 waves / SIMD
-    {64, 64, 16, 32, 32},    // 1: 4 waves, 1 wave / SIMD
-    {128, 64, 16, 64, 32},   // 2: 4 waves, 1 wave / SIMD
+    {0, 0, 0, 0, 0},         // 1: retired (one wave / SIMD, slower)
+    {0, 0, 0, 0, 0},         // 2: retired (128 x 64 blocks at one wave / SIMD, slower)
     {64, 64, 32, 32, 32},    // 3: 4 waves, 2 waves / SIMD
     {0, 0, 0, 0, 0},         // 4: retired (spilled)
     {0, 0, 0, 0, 0},         // 5: retired (spilled)
@@ -627,8 +650,6 @@ static hipError_t launch_kind(const GemmArgs& g, int cfg, hipStream_t s) {
         if (g.k >= 1024 && tiles >= 1024) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 0, 0, 1>(g, s);
       }
       return launch_one<KIND, 64, 64, 16, 32, 32, 2>(g, s);
-    case 1: return launch_one<KIND, 64, 64, 16, 32, 32, 1>(g, s);
-    case 2: return launch_one<KIND, 128, 64, 16, 64, 32, 1>(g, s);
     case 3:
       // Real products (one accumulator set) the same way.
       if constexpr (KIND == KIND_RR) {

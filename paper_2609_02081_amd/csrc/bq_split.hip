@@ -8,8 +8,9 @@
 //     q_1 = rint(2^b y), y_1 = y - q_1 2^-b, q_s = rint(2^{bs} y_{s-1}), ...
 //     so x = 2^e_i (sum_s q_s 2^{-bs} + remainder), |q_1| <= 2^{b-h},
 //     |q_s| <= 2^{b-1}; the digits are small integers, exact in BF16 (b = 7,
-//     h = 0), OCP FP8 E4M3 (b = 4, h = 0) or INT8 (b = 7, h = 1: one bit of
-//     headroom keeps the leading digit inside a signed byte);
+//     h = 0), OCP FP8 E4M3 (b = 5, h = 1: every digit within 16) or INT8
+//     (b = 7, h = 1: one bit of headroom keeps the leading digit inside a
+//     signed byte);
 //   * T_ij = 2^{e_i + f_j} sum_{d = 2}^{S+1} 2^{-bd} sum_{s + t = d} (Q_s R_t)_ij
 //     (pairs with s + t > S + 1 are dropped).
 // Each level d is accumulated by MFMA in FP32 (BF16/FP8) or int32 (INT8)
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(256) split_digits_left(const SplitArgs a, cons
   constexpr int ES = ET == 0 ? 2 : 1;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int64_t o = (int64_t)s * a.slice_stride * ES + digit_offset(a.tiled, r, kk0 * ES, a.kp * ES);
+    const int64_t o = (int64_t)s * a.slice_stride * ES + digit_offset(r, kk0 * ES, a.kp * ES);
     if constexpr (ET == 0) {
       i4v v;
 #pragma unroll
@@ -182,16 +183,13 @@ __global__ void __launch_bounds__(256) split_digits_right(const SplitArgs a, con
     const int rem = w % (64 * PIECES);
     const int cc = rem / PIECES, p = rem % PIECES;
     const i4v v = *reinterpret_cast<const i4v*>(&tile[s][cc][p * 16]);
-    const int64_t o = digit_offset(a.tiled, c0 + cc, k0 * ES + p * 16, a.kp * ES);
+    const int64_t o = digit_offset(c0 + cc, k0 * ES + p * 16, a.kp * ES);
     *reinterpret_cast<i4v*>(static_cast<unsigned char*>(out) + (int64_t)s * a.slice_stride * ES + o) = v;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Slice GEMM.  A 128 x 64 block tile (8 waves of 32 x 32, or 4 waves of
-// 64 x 32 for many slices), one MFMA k-step per LDS stage.  LDS holds all S slices of the A and B
-// tiles of that k-step; 16-byte (BF16, INT8) or 8-byte (FP8) chunks are
-// XOR-swizzled per row so fragment reads are free of bank conflicts.
+// Slice GEMM (BF16 and INT8 digits; FP8 digits: bq_split_f8.hip).
 //
 // MFMA layouts (checked with one-wave probes on gfx950):
 //   A: lane l holds row l % 16, k = E (l / 16) .. +E-1   (E elements/lane)
@@ -219,7 +217,11 @@ struct SliceTraits<2> {  // INT8 digits, v_mfma_i32_16x16x64_i8 (exact int32 sum
   }
 };
 
-constexpr double pow2neg(int e) { return 1.0 / (double)(1ull << e); }
+// 2^-e for 0 <= e <= 126 (levels reach e = b (S + 1) = 70): two shifts of at
+// most 63 bits each, so no shift reaches the width of the operand.
+constexpr double pow2neg(int e) {
+  return (1.0 / (double)(1ull << (e / 2))) * (1.0 / (double)(1ull << (e - e / 2)));
+}
 
 // Output of one wave tile (16 MI x 16 NI at rows r0.., columns c0..):
 // exponent scaling, then coef * T into every target block.
@@ -244,249 +246,6 @@ __device__ __forceinline__ void store_tile(const SliceGemmArgs& g, const d4s (&a
           g.c[q][off] = val;
         }
       }
-}
-
-
-
-template <int ET, int S, int WM, int MI, int CACHE_B, int NSTAGE, int WPE, int PERSIST>
-__global__ void __launch_bounds__(WM * 2 * 64) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-slice_gemm(const SliceGemmArgs g) {
-  typedef SliceTraits<ET> Tr;
-  typedef typename Tr::frag_t frag_t;
-  typedef typename Tr::acc_t acc_t;
-  constexpr int ES = Tr::ES, BK = Tr::KSTEP, CH = Tr::CH, BETA = Tr::BETA;
-  constexpr int NT = WM * 2 * 64;
-  constexpr int NI = 2;                // wave tile: (16 MI) x 32
-  constexpr int BM = 16 * MI * WM, BN = 64;
-  constexpr int ROWB = BK * ES;        // bytes per tile row: 64 (BF16, INT8) or 32 (FP8)
-  constexpr int NCH = ROWB / CH;       // chunks per row: 4
-  constexpr int A_BYTES = S * BM * ROWB;
-  constexpr int B_BYTES = S * BN * ROWB;
-  constexpr int STAGE = A_BYTES + B_BYTES;
-  constexpr int A_LD_TOTAL = A_BYTES / 16;  // 16-byte pieces per k-step
-  constexpr int A_LD = (A_LD_TOTAL + NT - 1) / NT;
-  constexpr int B_LD_TOTAL = B_BYTES / 16;
-  constexpr int B_LD = (B_LD_TOTAL + NT - 1) / NT;
-  static_assert(NCH == 4, "four chunks per row");
-  __shared__ __attribute__((aligned(16))) unsigned char lds[NSTAGE * STAGE];
-
-  const int tiles_m = (int)((g.m + BM - 1) / BM);
-  const int tiles_n = (int)((g.n + BN - 1) / BN);
-  // XCD-aware grouped tile order (as in the FP64 GEMM).
-  int tm, tn;
-  slice_tile_coords(tiles_m, tiles_n, tm, tn);
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave >> 1) * 16 * MI, wn0 = (wave & 1) * 32;
-  const int fr = lane & 15, fg = lane >> 4;
-
-  // Byte offset of chunk ch of row r (swizzled).
-  auto swz = [](int r, int ch) { return r * ROWB + swz_chunk<CH>(r, ch) * CH; };
-
-  // Global -> LDS staging.  Piece v = tid + i NT of a k-step covers 16 bytes
-  // of row r of slice s.  With PPR pieces per row and NT a multiple of PPR
-  // and of 16 rows, the per-lane part of every address is the same for all
-  // i (row tid / PPR, piece tid % PPR) and the rest is wave-uniform.
-  constexpr int PPR = ROWB / 16;                 // pieces per row: 4 or 2
-  constexpr int RPP = NT / PPR;                  // rows covered by one pass i
-  static_assert(RPP % 16 == 0, "swizzle needs whole 16-row groups per pass");
-  static_assert((RPP <= BM ? BM % RPP : RPP % BM) == 0 && (RPP <= BN ? BN % RPP : RPP % BN) == 0, "pass shape");
-  const int lr = tid / PPR, lp = tid % PPR;
-  // Lane part of the global offset for a tile of R rows (a pass may span
-  // several slices when it covers more rows than the tile has).
-  auto g_lane = [&](int R, int64_t slice_stride) -> int64_t {
-    return ((int64_t)(lr / R) * slice_stride + (int64_t)(lr % R) * g.kp) * ES + lp * 16;
-  };
-  const int64_t ga_lane = g_lane(BM, g.slice_stride_a);
-  const int64_t gb_lane = g_lane(BN, g.slice_stride_b);
-  // LDS position of (linear row lr, piece lp); the swizzle depends only on
-  // row bits 1..3, which whole-pass and whole-slice offsets (multiples of 16
-  // rows) leave unchanged.
-  const int l_lane_a = CH == 16 ? swz(lr, lp) : swz(lr, 2 * lp);
-  const int l_lane_a2 = CH == 16 ? 0 : swz(lr, 2 * lp + 1);  // second 8-byte half (FP8 only)
-  const unsigned char* ga = static_cast<const unsigned char*>(g.a) + m0 * g.kp * ES;
-  const unsigned char* gb = static_cast<const unsigned char*>(g.b) + n0 * g.kp * ES;
-  i4v ra[A_LD], rb[B_LD];
-  // Pass i of a tile of R rows starts at slice s, row r0.
-  auto pass_of = [&](int i, int R, int& s, int& r0) {
-    const int row_lin = i * RPP;
-    s = row_lin / R;
-    r0 = row_lin % R;
-  };
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      if (A_LD_TOTAL % NT == 0 || i * NT + tid < A_LD_TOTAL) {
-        int s, r0;
-        pass_of(i, BM, s, r0);
-        const unsigned char* base = ga + (s * g.slice_stride_a + (int64_t)r0 * g.kp + k0) * ES;
-        ra[i] = *reinterpret_cast<const i4v*>(base + ga_lane);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < B_LD; ++i) {
-      if (B_LD_TOTAL % NT == 0 || i * NT + tid < B_LD_TOTAL) {
-        int s, r0;
-        pass_of(i, BN, s, r0);
-        const unsigned char* base = gb + (s * g.slice_stride_b + (int64_t)r0 * g.kp + k0) * ES;
-        rb[i] = *reinterpret_cast<const i4v*>(base + gb_lane);
-      }
-    }
-  };
-  auto put = [&](unsigned char* base, i4v x) {
-    if constexpr (CH == 16) {
-      *reinterpret_cast<i4v*>(base + l_lane_a) = x;
-    } else {
-      *reinterpret_cast<i2v*>(base + l_lane_a) = i2v{x[0], x[1]};
-      *reinterpret_cast<i2v*>(base + l_lane_a2) = i2v{x[2], x[3]};
-    }
-  };
-  auto lstore = [&](int st) {
-    unsigned char* base = lds + st * STAGE;
-#pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      if (A_LD_TOTAL % NT == 0 || i * NT + tid < A_LD_TOTAL) {
-        int s, r0;
-        pass_of(i, BM, s, r0);
-        put(base + s * BM * ROWB + r0 * ROWB, ra[i]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < B_LD; ++i) {
-      if (B_LD_TOTAL % NT == 0 || i * NT + tid < B_LD_TOTAL) {
-        int s, r0;
-        pass_of(i, BN, s, r0);
-        put(base + A_BYTES + s * BN * ROWB + r0 * ROWB, rb[i]);
-      }
-    }
-  };
-
-  d4s acc[MI][NI];
-#pragma unroll
-  for (int i = 0; i < MI; ++i)
-#pragma unroll
-    for (int j = 0; j < NI; ++j) acc[i][j] = d4s{0.0, 0.0, 0.0, 0.0};
-
-  // Level sums (PERSIST): level d = s + t in lvl[d - 2].
-  acc_t lvl[PERSIST ? S : 1][MI][NI];
-#pragma unroll
-  for (int d = 0; d < (PERSIST ? S : 1); ++d)
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
-#pragma unroll
-      for (int j = 0; j < NI; ++j) lvl[d][i][j] = acc_t{0, 0, 0, 0};
-  int since = 0;
-
-  const int64_t nk = g.kp / BK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int st = NSTAGE == 2 ? (int)(kt & 1) : 0;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-    const unsigned char* base = lds + st * STAGE;
-    if constexpr (PERSIST) {
-      // Every B fragment of the k-step stays in registers; the A fragments
-      // of one slice at a time.  Level sums live across k-steps.
-      frag_t fbc[S][NI];
-#pragma unroll
-      for (int t = 0; t < S; ++t)
-#pragma unroll
-        for (int j = 0; j < NI; ++j)
-          fbc[t][j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + t * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
-#pragma unroll
-      for (int s = 1; s <= S; ++s) {
-        frag_t fa[MI];
-#pragma unroll
-        for (int i = 0; i < MI; ++i)
-          fa[i] = *reinterpret_cast<const frag_t*>(base + (s - 1) * BM * ROWB + swz(wm0 + i * 16 + fr, fg));
-#pragma unroll
-        for (int t = 1; t <= S + 1 - s; ++t)
-#pragma unroll
-          for (int i = 0; i < MI; ++i)
-#pragma unroll
-            for (int j = 0; j < NI; ++j) lvl[s + t - 2][i][j] = Tr::mfma(fa[i], fbc[t - 1][j], lvl[s + t - 2][i][j]);
-      }
-      if (++since == g.kflush || kt + 1 == nk) {
-        since = 0;
-#pragma unroll
-        for (int d = 2; d <= S + 1; ++d) {
-          const double sc = pow2neg(BETA * d);
-#pragma unroll
-          for (int i = 0; i < MI; ++i)
-#pragma unroll
-            for (int j = 0; j < NI; ++j) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v)
-                acc[i][j][v] = __builtin_fma((double)lvl[d - 2][i][j][v], sc, acc[i][j][v]);
-              lvl[d - 2][i][j] = acc_t{0, 0, 0, 0};
-            }
-        }
-      }
-    } else {
-      frag_t fa[S][MI];
-      frag_t fbc[CACHE_B ? S : 1][NI];
-  #pragma unroll
-      for (int s = 0; s < S; ++s) {
-  #pragma unroll
-        for (int i = 0; i < MI; ++i)
-          fa[s][i] = *reinterpret_cast<const frag_t*>(base + s * BM * ROWB + swz(wm0 + i * 16 + fr, fg));
-        if constexpr (CACHE_B) {
-  #pragma unroll
-          for (int j = 0; j < NI; ++j)
-            fbc[s][j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + s * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
-        }
-      }
-      // Levels d = 2 .. S+1.  The MFMAs of level d are issued while the sums of
-      // level d-1 are flushed into FP64 (two accumulator sets), so the flush's
-      // VALU work overlaps the matrix pipe; scheduling barriers between levels
-      // keep register use bounded.
-      acc_t lv[2][MI][NI];
-      auto flush = [&](const acc_t (&x)[MI][NI], int d) {
-        const double sc = pow2neg(BETA * d);
-  #pragma unroll
-        for (int i = 0; i < MI; ++i)
-  #pragma unroll
-          for (int j = 0; j < NI; ++j)
-  #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[i][j][v] = __builtin_fma((double)x[i][j][v], sc, acc[i][j][v]);
-      };
-  #pragma unroll
-      for (int d = 2; d <= S + 1; ++d) {
-        __builtin_amdgcn_sched_barrier(0);
-        const int cur = d & 1;
-  #pragma unroll
-        for (int i = 0; i < MI; ++i)
-  #pragma unroll
-          for (int j = 0; j < NI; ++j) lv[cur][i][j] = acc_t{0, 0, 0, 0};
-  #pragma unroll
-        for (int s = 1; s < d; ++s) {
-          const int t = d - s;
-          if (s > S || t > S) continue;
-          frag_t fb[NI];
-  #pragma unroll
-          for (int j = 0; j < NI; ++j) {
-            if constexpr (CACHE_B)
-              fb[j] = fbc[t - 1][j];
-            else
-              fb[j] = *reinterpret_cast<const frag_t*>(base + A_BYTES + (t - 1) * BN * ROWB + swz(wn0 + j * 16 + fr, fg));
-          }
-  #pragma unroll
-          for (int i = 0; i < MI; ++i)
-  #pragma unroll
-            for (int j = 0; j < NI; ++j) lv[cur][i][j] = Tr::mfma(fa[s - 1][i], fb[j], lv[cur][i][j]);
-        }
-        if (d > 2) flush(lv[cur ^ 1], d - 1);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      flush(lv[(S + 1) & 1], S + 1);
-    }
-    if (NSTAGE == 1) __syncthreads();
-    if (kt + 1 < nk) lstore(NSTAGE == 2 ? (st ^ 1) : 0);
-    __syncthreads();
-  }
-
-  store_tile<MI, NI>(g, acc, m0 + wm0, n0 + wn0, fr, fg);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,7 +286,7 @@ slice_gemm_dma(const SliceGemmArgs g) {
   const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
   const int fr = lane & 15, fg = lane >> 4;
 
-  // Loads: the digits are tiled (slice_tile_offset), so the tile of slice s
+  // Loads: the digits are tiled (digit_offset), so the tile of slice s
   // for k-step kt is 4 KB contiguous, already in LDS order; thread tid copies
   // its bytes 16 tid .. 16 tid + 15.  Buffer loads with one resource per
   // slice and block row (column) tile: its nk tiles, so any offset past them
@@ -626,198 +385,6 @@ slice_gemm_dma(const SliceGemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Slice GEMM on the 32 x 32 MFMA shapes (BF16: v_mfma_f32_32x32x16_bf16,
-// INT8: v_mfma_i32_32x32x32_i8; checked with one-wave probes: A lane l holds
-// row l % 32, k = 16 (l / 32) bytes on; B the same per column; D lane l,
-// element v holds row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32).  A k-step
-// is 32 bytes of each digit row, so a 128 x 64 block of 8 waves (32 x 32 each,
-// two waves per SIMD) keeps two LDS stages of S slices within 160 KB and
-// moves a quarter fewer bytes per MFMA than the 64 x 64 block.  Digits in the
-// tiled layout of 32-byte rows; per k-step a stage holds S A tiles (128 rows,
-// two 64-row tiles) and S B tiles (64 rows), copied straight into LDS in 1 KB
-// pieces, wave w taking pieces w, w + 8, ...  Level sums as in
-// slice_gemm_dma.
-// ---------------------------------------------------------------------------
-typedef int i16v __attribute__((ext_vector_type(16)));
-typedef float f16v __attribute__((ext_vector_type(16)));
-
-
-template <int ET>
-struct SliceTraits32;
-template <>
-struct SliceTraits32<0> {
-  static constexpr int ES = 2, BETA = SliceTraits<0>::BETA;
-  typedef bf16x8 frag_t;
-  typedef f16v acc_t;
-  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct SliceTraits32<2> {
-  static constexpr int ES = 1, BETA = SliceTraits<2>::BETA;
-  typedef i4v frag_t;
-  typedef i16v acc_t;
-  __device__ static acc_t mfma(frag_t a, frag_t b, acc_t c) {
-    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
-  }
-};
-
-// Output of one 32 x 32 wave tile at (r0, c0): exponent scaling, then
-// coef * T into every target block.
-__device__ __forceinline__ void store_tile32(const SliceGemmArgs& g, const double (&acc)[16], int64_t r0, int64_t c0,
-                                             int lane) {
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int64_t r = r0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    const int64_t c = c0 + (lane & 31);
-    if (r >= g.m || c >= g.n) continue;
-    const int ea = g.ea[r], eb = g.eb[c];
-    const double t = exp_scaled(acc[v], ea, eb, 0);
-    const int64_t off = r * g.ldc + c;
-    for (int q = 0; q < g.ntgt; ++q) {
-      double val = g.coef[q] * t;
-      if (g.mode[q] == TGT_ACCUM) val += g.c[q][off];
-      g.c[q][off] = val;
-    }
-  }
-}
-
-template <int ET, int S>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
-slice_gemm_x32(const SliceGemmArgs g) {
-  typedef SliceTraits32<ET> Tr;
-  typedef typename Tr::frag_t frag_t;
-  typedef typename Tr::acc_t acc_t;
-  constexpr int ES = Tr::ES, BETA = Tr::BETA;
-  constexpr int BM = 128, BN = 64, RB = 32, TILE = 64 * RB;  // 2 KB per 64-row tile
-  constexpr int A_SLICE = BM * RB, B_SLICE = BN * RB;
-  constexpr int A_BYTES = S * A_SLICE;
-  constexpr int STAGE = A_BYTES + S * B_SLICE;
-  constexpr int PIECES = STAGE / 1024;  // 6 S
-  // Three stages when they fit: the loads of k-step kt + 2 go out while kt
-  // is computed, so a load has two k-steps to land.
-  constexpr int NST = 3 * STAGE <= 160 * 1024 ? 3 : 2;
-  // Every wave issues the same number of loads per stage (the last ones
-  // repeat a piece of its own: the same bytes to the same place), so the
-  // wait for a stage is one immediate count.
-  constexpr int NPW = (PIECES + 7) / 8;
-  static_assert(2 * STAGE <= 160 * 1024, "two stages must fit LDS");
-  __shared__ __attribute__((aligned(16))) unsigned char lds[NST * STAGE];
-
-  const int tiles_m = (int)((g.m + BM - 1) / BM);
-  const int tiles_n = (int)((g.n + BN - 1) / BN);
-  int tm, tn;
-  slice_tile_coords(tiles_m, tiles_n, tm, tn);
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: one buffer resource per load
-  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
-  const int fr = lane & 31, fg = lane >> 5;
-
-  const int64_t nk = g.kp * ES / RB;
-  const int64_t run = nk * TILE;  // bytes of one 64-row tile's k-run
-  const unsigned char* ga = static_cast<const unsigned char*>(g.a) + (int64_t)(2 * tm) * run;
-  const unsigned char* gb = static_cast<const unsigned char*>(g.b) + (int64_t)tn * run;
-  const int64_t sa = g.slice_stride_a * ES, sb = g.slice_stride_b * ES;
-  const int nrec_a = (int)(uint32_t)(2 * run), nrec_b = (int)(uint32_t)run;  // num_records is unsigned
-  // 1 KB piece p of a stage: A slice p / 4, quarter p % 4 (64-row tile
-  // (p % 4) / 2, half p % 2); then B slice (p - 4S) / 2, half p % 2.
-  auto dma = [&](int p, int64_t kt, int st) {
-    const unsigned char* base;
-    int nrec, voff, loff;
-    if (p < 4 * S) {
-      const int sl = p >> 2, q = p & 3;
-      base = ga + sl * sa;
-      nrec = nrec_a;
-      voff = (int)((q >> 1) * run) + (q & 1) * 1024 + lane * 16;
-      loff = sl * A_SLICE + q * 1024;
-    } else {
-      const int pb = p - 4 * S, sl = pb >> 1;
-      base = gb + sl * sb;
-      nrec = nrec_b;
-      voff = (pb & 1) * 1024 + lane * 16;
-      loff = A_BYTES + sl * B_SLICE + (pb & 1) * 1024;
-    }
-    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, nrec, 0x00020000);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_ptr)(lds + st * STAGE + loff), 16, voff,
-                                             (int)(kt * TILE), 0, 0);
-  };
-  auto piece = [&](int i) {
-    const int p = wave + 8 * i;
-    return p < PIECES ? p : wave;
-  };
-  auto frag = [&](const unsigned char* tile, int row) {
-    return *reinterpret_cast<const frag_t*>(tile + row * RB + swz_chunk32(row, fg) * 16);
-  };
-
-  double acc[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.0;
-
-#pragma unroll
-  for (int i = 0; i < NPW; ++i) dma(piece(i), 0, 0);
-  if constexpr (NST == 3) {
-#pragma unroll
-    for (int i = 0; i < NPW; ++i) dma(piece(i), nk > 1 ? 1 : 0, 1);
-    wait_vm<NPW>();
-  } else {
-    wait_vm<0>();
-  }
-  block_sync();
-  for (int64_t k0 = 0; k0 < nk; k0 += g.kflush) {
-    const int64_t k1 = min(nk, k0 + (int64_t)g.kflush);
-    acc_t lvl[S];
-#pragma unroll
-    for (int d = 0; d < S; ++d)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) lvl[d][v] = 0;
-    for (int64_t kt = k0; kt < k1; ++kt) {
-      const int st = (int)(kt % NST);
-      const int sn = NST == 3 ? (st == 0 ? 2 : st - 1) : (st ^ 1);  // stage of k-step kt + NST - 1
-      // Past the end the last k-step is reloaded into a stage nobody reads.
-      const int64_t knext = kt + NST - 1 < nk ? kt + NST - 1 : nk - 1;
-      const unsigned char* ta = lds + st * STAGE;
-      const unsigned char* tb = ta + A_BYTES;
-      frag_t fb[S];
-#pragma unroll
-      for (int t = 0; t < S; ++t) fb[t] = frag(tb + t * B_SLICE, wn0 + fr);
-      frag_t fa = frag(ta, wm0 + fr);
-      int q = 0;  // loads of k-step kt + NST - 1 issued so far
-#pragma unroll
-      for (int s = 1; s <= S; ++s) {
-        frag_t fa_next = fa;
-        if (s < S) fa_next = frag(ta + s * A_SLICE, wm0 + fr);
-#pragma unroll
-        for (int t = 1; t <= S + 1 - s; ++t) {
-          lvl[s + t - 2] = Tr::mfma(fa, fb[t - 1], lvl[s + t - 2]);
-          if (q < NPW) {
-            dma(piece(q), knext, sn);
-            ++q;
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-        fa = fa_next;
-      }
-      for (; q < NPW; ++q) dma(piece(q), knext, sn);
-      // Stage kt + 1 is complete once at most this k-step's loads are out.
-      wait_vm<NST == 3 ? NPW : 0>();
-      block_sync();
-    }
-#pragma unroll
-    for (int d = 2; d <= S + 1; ++d) {
-      const double sc = pow2neg(BETA * d);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = __builtin_fma((double)lvl[d - 2][v], sc, acc[v]);
-    }
-  }
-  // No load may still be writing this block's LDS when it ends.
-  wait_vm<0>();
-
-  store_tile32(g, acc, m0 + wm0, n0 + wn0, lane);
-}
-
-// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_split_exponents(const SplitArgs& a, int* exps, hipStream_t st) {
@@ -851,82 +418,19 @@ static hipError_t launch_split_s(const SplitArgs& a, int* exps, void* out, hipSt
   return hipGetLastError();
 }
 
-// Block shapes, all with 32 x 32 wave tiles:
-//   variant 0: 8 waves (128 x 64 outputs), 2 waves/SIMD, B fragments read
-//              from LDS for every slice pair, levels flushed every k-step;
-//   variant 1: 4 waves (64 x 64 outputs), 1 wave/SIMD, every A and B
-//              fragment of the k-step cached in registers, levels flushed
-//              every k-step;
-//   variant 2: as variant 1, with the level sums kept across k-steps and
-//              flushed to FP64 every slice_flush_steps k-steps;
-//   variant 3: slice_gemm_dma (BF16, INT8);
-//   variant 4: slice_gemm_x32 (BF16, INT8).
-template <int ET, int S, int V>
-static hipError_t launch_slice_v(const SliceGemmArgs& g, hipStream_t st) {
-  typedef SliceTraits<ET> Tr;
-  constexpr int WM = V == 0 ? 4 : 2, CACHE_B = V == 0 ? 0 : 1, WPE = V == 0 ? 2 : 1, PERSIST = V == 2 ? 1 : 0;
-  constexpr int BM = 32 * WM;
-  constexpr int STAGE = S * (BM + 64) * Tr::KSTEP * Tr::ES;
-  constexpr int NSTAGE = 2 * STAGE <= 160 * 1024 ? 2 : 1;
-  static_assert(STAGE <= 160 * 1024, "slice tile does not fit LDS");
-  const int64_t tiles = ((g.m + BM - 1) / BM) * ((g.n + 63) / 64);
+template <int ET, int S>
+static hipError_t launch_slice_s(const SliceGemmArgs& g, hipStream_t st) {
+  const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
   if (tiles <= 0) return hipSuccess;
   if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((slice_gemm<ET, S, WM, 2, CACHE_B, NSTAGE, WPE, PERSIST>), dim3((unsigned)tiles),
-                     dim3(WM * 2 * 64), 0, st, g);
+  hipLaunchKernelGGL((slice_gemm_dma<ET, S>), dim3((unsigned)tiles), dim3(256), 0, st, g);
   return hipGetLastError();
-}
-
-// Default: the direct-to-LDS shape for BF16 and INT8 digits.  FP8 digits
-// have one shape, slice_gemm_f8 (variant 5, bq_split_f8.hip).
-int default_slice_variant(int et, int S) {
-  (void)S;
-  return et == 1 ? 5 : 3;
-}
-
-int resolve_slice_variant(int et, int S, int variant) {
-  if (et == 1) return 5;
-  if (variant < 0 || variant > 4) return default_slice_variant(et, S);
-  if (variant == 4 && S > 8) return 3;  // the 32 x 32 shape is built up to 8 slices
-  if (variant == 0 && S > 6) return default_slice_variant(et, S);
-  return variant;
-}
-
-int slice_variant_tiled(int variant) { return (variant == 3 || variant == 5) ? 1 : (variant == 4 ? 2 : 0); }
-
-template <int ET, int S>
-static hipError_t launch_slice_s(const SliceGemmArgs& g, int variant, hipStream_t st) {
-  variant = resolve_slice_variant(ET, S, variant);
-  if (variant == 0) {
-    if constexpr (S <= 6) return launch_slice_v<ET, S, 0>(g, st);
-    else return hipErrorInvalidValue;
-  }
-  if (variant == 2) return launch_slice_v<ET, S, 2>(g, st);
-  if (variant == 4) {
-    if constexpr (S <= 8) {
-      const int64_t tiles = ((g.m + 127) / 128) * ((g.n + 63) / 64);
-      if (tiles <= 0) return hipSuccess;
-      if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((slice_gemm_x32<ET, S>), dim3((unsigned)tiles), dim3(512), 0, st, g);
-      return hipGetLastError();
-    } else {
-      return hipErrorInvalidValue;
-    }
-  }
-  if (variant == 3) {
-    const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
-    if (tiles <= 0) return hipSuccess;
-    if (tiles > 0x7fffffff || g.kflush < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((slice_gemm_dma<ET, S>), dim3((unsigned)tiles), dim3(256), 0, st, g);
-    return hipGetLastError();
-  }
-  return launch_slice_v<ET, S, 1>(g, st);
 }
 
 int slice_block_rows(int et, int S) {
   (void)et;
   (void)S;
-  return 128;  // digit rows are padded to 128, a multiple of both shapes
+  return 128;  // digit rows are padded to 128, a multiple of every block's rows
 }
 
 int slice_kstep(int et) {
@@ -965,10 +469,10 @@ hipError_t launch_split(int et, int S, const SplitArgs& a, int* exps, void* out,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_slice_gemm(int et, int S, int variant, const SliceGemmArgs& g, hipStream_t st) {
+hipError_t launch_slice_gemm(int et, int S, const SliceGemmArgs& g, hipStream_t st) {
   if (et == 1) return launch_slice_gemm_f8(S, g, st);
 #define X(E, SS) \
-  if (et == E && S == SS) return launch_slice_s<E, SS>(g, variant, st);
+  if (et == E && S == SS) return launch_slice_s<E, SS>(g, st);
   BQ_SPLIT_CASES(0, X)
   BQ_SPLIT_CASES(2, X)
   X(2, 9)

@@ -59,30 +59,18 @@ __device__ __forceinline__ int swz_chunk(int r, int ch) {
   else return ch ^ ((r >> 2) & 3);
 }
 
-// Tiled digit layouts (direct-to-LDS slice GEMMs): within one slice, the 64
-// rows x one k-step (RB = 64 or 32 bytes per row) of row tile rt, k-step kt
-// form one 64 RB-byte block at (rt * nk + kt) * 64 RB, stored in the LDS
-// order (row r at r * RB, logical 16-byte chunk ch at the swizzled position),
-// so that a straight copy lands the tile ready for fragment reads.
-// Rows of 32 bytes (two chunks): a 16-byte fragment read has 8 lanes on 8
-// consecutive rows at one chunk, rows r and r + 4 share banks, so the chunk
-// position flips with row bit 2.
-__device__ __forceinline__ int swz_chunk32(int r, int ch) { return ch ^ ((r >> 2) & 1); }
-
-template <int RB>
-__device__ __forceinline__ int64_t slice_tile_offset(int64_t r, int64_t byte_in_row, int64_t row_bytes) {
+// Tiled digit layout (direct-to-LDS slice and residue GEMMs): within one
+// slice, the 64 rows x one k-step (64 bytes per row) of row tile rt, k-step
+// kt form one 4 KB block at (rt * nk + kt) * 4096, stored in the LDS order
+// (row r at r * 64, logical 16-byte chunk ch at the swizzled position), so
+// that a straight copy lands the tile ready for fragment reads.  Byte
+// offset of the digit at (row r, byte b of the row) in one slice whose rows
+// hold row_bytes.
+__device__ __forceinline__ int64_t digit_offset(int64_t r, int64_t byte_in_row, int64_t row_bytes) {
+  constexpr int RB = 64;
   const int64_t nk = row_bytes / RB, kt = byte_in_row / RB;
   const int rr = (int)(r & 63), b = (int)(byte_in_row % RB);
-  const int pos = RB == 64 ? swz_chunk<16>(rr, b >> 4) : swz_chunk32(rr, b >> 4);
-  return ((r >> 6) * nk + kt) * (64 * RB) + rr * RB + pos * 16 + (b & 15);
-}
-
-// Byte offset of the digit at (row r, byte b of the row) in one slice, for
-// layout `tiled` (0: row-major with rows of row_bytes).
-__device__ __forceinline__ int64_t digit_offset(int tiled, int64_t r, int64_t b, int64_t row_bytes) {
-  if (tiled == 1) return slice_tile_offset<64>(r, b, row_bytes);
-  if (tiled == 2) return slice_tile_offset<32>(r, b, row_bytes);
-  return r * row_bytes + b;
+  return ((r >> 6) * nk + kt) * (64 * RB) + rr * RB + swz_chunk<16>(rr, b >> 4) * 16 + (b & 15);
 }
 
 // Block -> output tile, XCD-aware and grouped by 8 tile rows (as in the

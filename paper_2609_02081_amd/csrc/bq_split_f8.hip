@@ -8,7 +8,7 @@
 //
 // Block: a 64 x 64 output tile, 4 waves of 32 x 32 (one MFMA per slice pair
 // and 64-deep k-step), one wave per SIMD.  Digits are in the tiled layout of
-// 64-byte rows (split kernels with tiled = 1): the 64 rows x one k-step of a
+// 64-byte rows (digit_offset): the 64 rows x one k-step of a
 // slice are 4 KB contiguous, already in LDS order, and move straight into LDS
 // (buffer_load_dwordx4 ... lds, thread tid copying bytes 16 tid .. 16 tid +
 // 15 of each tile).

@@ -48,36 +48,47 @@ def test_integer_bit_exact(bq, kind, S):
     assert np.array_equal(run(bq, A, B, kind, S), oracle.gemm(A, B))
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
-@pytest.mark.parametrize("kind,S", [("bf16", 3), ("bf16", 6), ("bf16", 8), ("fp8", 1), ("fp8", 5), ("fp8", 9),
-                                    ("fp8", 12), ("fp8", 13), ("int8", 4), ("int8", 7), ("int8", 9)])
-def test_matches_cpu_split_model(bq, kind, S, variant, monkeypatch):
-    """Every slice-GEMM block shape (the 8-wave one exists up to S = 6; BF16
-    and INT8 digits have five shapes, FP8 digits one) against the CPU split
-    model; ragged shape."""
-    if kind == "fp8" and variant != "0":
-        pytest.skip("FP8 digits have one block shape (the variant switch does not apply)")
-    if variant == "0" and kind != "fp8" and S > 6:
-        pytest.skip("8-wave shape not built for this many slices")
-    if variant == "4" and S > 8:
-        pytest.skip("the 32 x 32 shape is built up to 8 slices")
-    monkeypatch.setenv("BQ_SLICE_VARIANT", variant)
+@pytest.mark.parametrize("kind,S", [("bf16", 1), ("bf16", 3), ("bf16", 6), ("bf16", 8), ("fp8", 1), ("fp8", 5),
+                                    ("fp8", 9), ("fp8", 12), ("fp8", 13), ("int8", 1), ("int8", 4), ("int8", 7),
+                                    ("int8", 9)])
+def test_matches_cpu_split_model(bq, kind, S):
+    """The slice GEMM of each digit type against the CPU split model, from
+    one slice up to the most each type is built for (INT8 at 9 slices
+    scales its last level by 2^-70); ragged shape."""
     A, B = inputs.pair(130, 100, 70, "uniform", seed=13)
-    print(f"split {kind} S={S} variant {variant} vs model", flush=True)
+    print(f"split {kind} S={S} vs model", flush=True)
     ref = bilinear(A, B, Counter(lambda x, y: ozaki.product(x, y, kind, S)))
     got = run(bq, A, B, kind, S)
     assert oracle.rel_frobenius(got, ref) <= 1e-14
 
 
-@pytest.mark.parametrize("variant", ["2", "3", "4"])
+@pytest.mark.parametrize("kind,S", [("bf16", 8), ("fp8", 13), ("int8", 9), ("int8", 1)])
+def test_deepest_level_scale(bq, kind, S):
+    """A real product carried by one digit pair alone, slice S of the left
+    operand with slice 1 of the right (level S + 1, scale 2^-beta (S + 1):
+    2^-63 for BF16, 2^-70 for FP8 at 13 and INT8 at 9 slices): the left row
+    [0.75, 2^(h - beta S)], the right column [0, 2^-6].  The result is the
+    exact product, so a level dropped or scaled wrong shows."""
+    import torch
+
+    beta, head = ozaki.BETA[kind], ozaki.HEAD[kind]
+    A = np.zeros((8, 1, 2))
+    A[0, 0] = [0.75, 2.0 ** (head - beta * S)]
+    B = np.zeros((8, 2, 1))
+    B[0, :, 0] = [0.0, 2.0 ** -6]
+    C = bq.bq_gemm(torch.from_numpy(A).to("cuda"), torch.from_numpy(B).to("cuda"), prec=PRECS[kind], slices=S,
+                   mask_a=0x01, mask_b=0x01)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy()
+    assert got[0, 0, 0] == A[0, 0, 1] * B[0, 1, 0], (got[0, 0, 0], A[0, 0, 1] * B[0, 1, 0])
+    assert not np.any(got[1:])
+
+
 @pytest.mark.parametrize("flush", ["1", "3"])
-@pytest.mark.parametrize("kind,S", [("bf16", 8), ("fp8", 9), ("int8", 8)])
-def test_level_flush_interval(bq, kind, S, flush, variant, monkeypatch):
+@pytest.mark.parametrize("kind,S", [("bf16", 8), ("fp8", 9), ("int8", 8), ("int8", 9)])
+def test_level_flush_interval(bq, kind, S, flush, monkeypatch):
     """Level sums kept across k-steps and flushed every 1 or 3 k-steps (K =
     700: several flushes and a partial last interval) against the model."""
-    if variant in ("3", "4") and kind == "fp8":
-        pytest.skip("FP8 digits have one block shape (the variant switch does not apply)")
-    monkeypatch.setenv("BQ_SLICE_VARIANT", variant)
     monkeypatch.setenv("BQ_SLICE_FLUSH", flush)
     A, B = inputs.pair(40, 700, 36, "logspread", seed=16)
     print(f"split {kind} S={S} flush {flush} vs model", flush=True)

@@ -122,3 +122,25 @@ def test_zero_rows_and_columns():
     X = np.zeros((5, 7)); X[1] = np.arange(7) + 1.0
     Y = np.zeros((7, 4)); Y[:, 2] = 1.0
     assert np.array_equal(ozaki.product(X, Y, "bf16", 4), X @ Y)
+
+
+def deepest_level_pair(kind, S):
+    """A 1 x 2 times 2 x 1 product carried by one digit pair alone: the
+    left row [0.75, x] puts x = 2^(h - beta S) in its last slice only, the
+    right column [0, 2^-6] puts 2^-6 in its first slice, so the product
+    x 2^-6 lives in level S + 1 (scale 2^-beta (S + 1)) and nowhere else."""
+    beta, head = ozaki.BETA[kind], ozaki.HEAD[kind]
+    X = np.array([[0.75, 2.0 ** (head - beta * S)]])
+    Y = np.array([[0.0], [2.0 ** -6]])
+    return X, Y
+
+
+@pytest.mark.parametrize("kind,S", KINDS + [("bf16", 1), ("int8", 1)])
+def test_deepest_level_is_kept(kind, S):
+    X, Y = deepest_level_pair(kind, S)
+    Qx, _, _ = ozaki.digits(X, ozaki.BETA[kind], S, axis=1, head=ozaki.HEAD[kind])
+    col = [int(q[0, 1]) for q in Qx]
+    assert col[:-1] == [0] * (S - 1) and col[-1] != 0
+    T = ozaki.product(X, Y, kind, S)
+    assert T[0, 0] == X[0, 1] * Y[1, 0] != 0.0
+
