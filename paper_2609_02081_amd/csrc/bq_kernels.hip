@@ -108,6 +108,37 @@ __device__ __forceinline__ void load_pairs(double (&dst)[2 * PAIRS], const doubl
   }
 }
 
+// The same pattern (MODE 0) through a buffer resource: the per-thread byte
+// offsets voff[i] (fixed for the tile) are computed once, the k-step moves
+// only the resource's scalar base, so a load costs no vector address work.
+// The base must be the same in every lane (one tile per block).
+template <int PAIRS>
+__device__ __forceinline__ void load_pairs_rsrc(double (&dst)[2 * PAIRS], const double* base,
+                                                const uint32_t (&voff)[PAIRS]) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+#pragma unroll
+  for (int i = 0; i < PAIRS; ++i) {
+    const d2 x = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff[i], 0, 0));
+    dst[2 * i] = x[0];
+    dst[2 * i + 1] = x[1];
+  }
+}
+
+// A pointer that is the same in every lane, read from the first lane when
+// UNI = 1 so that the compiler keeps it (and what is computed from it) in
+// scalar registers: the batched kernel reads its arguments from memory,
+// the single-call kernel has them in kernel arguments, already scalar.
+template <int UNI>
+__device__ __forceinline__ const double* uniform_ptr(const double* p) {
+  if constexpr (UNI) {
+    const uint64_t b = reinterpret_cast<uint64_t>(p);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return reinterpret_cast<const double*>(lo | (hi << 32));
+  }
+  return p;
+}
+
 // One output tile (m0, n0) of the complex product described by g: K loop and
 // epilogue.  Every thread of the block must call it (it synchronises).
 // TA / TB: the left / right operand is stored transposed (op T or H: the
@@ -115,8 +146,9 @@ __device__ __forceinline__ void load_pairs(double (&dst)[2 * PAIRS], const doubl
 // DEEP: two register sets, global loads two k-steps ahead and the LDS store
 // of the next stage three quarters of the way through the current k-step's
 // MFMAs (32 more registers; used where they fit without spills).
-// ADD: targets may carry an addend matrix (Target::sr / si, scaled by sc,
-// leading dimension GemmArgs::ldadd); only the batched kernel uses it.
+// ADD: the batched kernel's tile: targets may carry an addend matrix
+// (Target::sr / si, scaled by sc, leading dimension GemmArgs::ldadd), and
+// the arguments come from a device table (operand bases made scalar).
 template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0, int DEEP = 0, int ADD = 0>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
                                           TileSmem<KIND, BM, BN, BK>& sm) {
@@ -156,14 +188,30 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   // Per-tile base pointers: all further offsets stay small (32-bit).
   const int64_t a_off = TA ? m0 : m0 * g.lda;
   const int64_t b_off = TB ? n0 * g.ldb : n0;
-  const double* pa[2] = {g.lr + a_off, HAS_LI ? g.li + a_off : nullptr};
-  const double* pb[2] = {g.rr + b_off, HAS_RI ? g.ri + b_off : nullptr};
+  const double* pa[2] = {uniform_ptr<ADD>(g.lr + a_off), HAS_LI ? uniform_ptr<ADD>(g.li + a_off) : nullptr};
+  const double* pb[2] = {uniform_ptr<ADD>(g.rr + b_off), HAS_RI ? uniform_ptr<ADD>(g.ri + b_off) : nullptr};
   const int64_t mrem = g.m - m0;
   const int64_t nrem = g.n - n0;
   // Interior tiles load without bounds checks (16-byte loads when the rows
   // are 16-byte aligned).
   const bool interior = mrem >= BM && nrem >= BN;
   const bool fast = g.vec && interior;
+  // Byte offsets of this thread's pairs in the stored tiles (16-byte path):
+  // usable through a buffer resource while the farthest stays below 2^31.
+  const int64_t a_span = (TA ? (int64_t)(BK - 1) * g.lda + BM : (int64_t)(BM - 1) * g.lda + BK) * 8;
+  const int64_t b_span = (TB ? (int64_t)(BN - 1) * g.ldb + BK : (int64_t)(BK - 1) * g.ldb + BN) * 8;
+  const bool rsrc_ok = fast && a_span < 0x7fffffff && b_span < 0x7fffffff;
+  uint32_t voff_a[A_PAIRS], voff_b[B_PAIRS];
+#pragma unroll
+  for (int i = 0; i < A_PAIRS; ++i) {
+    const int v = tid + i * NT;
+    voff_a[i] = (uint32_t)(((v / (AC / 2)) * (uint32_t)g.lda + 2 * (v % (AC / 2))) * 8u);
+  }
+#pragma unroll
+  for (int i = 0; i < B_PAIRS; ++i) {
+    const int v = tid + i * NT;
+    voff_b[i] = (uint32_t)(((v / (BC / 2)) * (uint32_t)g.ldb + 2 * (v % (BC / 2))) * 8u);
+  }
 
   // Register sets for the global tiles (DEEP: k-step j goes through set j % 2).
   double ra0[NA][2 * A_PAIRS], ra1[NA][2 * A_PAIRS];
@@ -285,19 +333,40 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
       }
   };
 
+  // Loads of k-step kn: any k-step (bounds-checked where the tile needs
+  // it), or a full k-step of an interior tile with 16-byte rows through
+  // buffer resources.  Such tiles run their full k-steps in a loop of their
+  // own, so the steady state carries neither the checked loads nor their
+  // registers; the last k-steps and other tiles run the general loop.
+  auto load_any = [&](int64_t kn, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
+    if (kn < nk) gload(kn * BK, ra, rb);
+  };
+  auto load_full = [&](int64_t kn, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
+    const int64_t k0 = kn * BK;
+#pragma unroll
+    for (int p = 0; p < NA; ++p) load_pairs_rsrc<A_PAIRS>(ra[p], pa[p] + (TA ? k0 * g.lda : k0), voff_a);
+#pragma unroll
+    for (int p = 0; p < NB; ++p) load_pairs_rsrc<B_PAIRS>(rb[p], pb[p] + (TB ? k0 : k0 * g.ldb), voff_b);
+  };
+  const int64_t nkf = g.k / BK;  // full k-steps
+
   if constexpr (!DEEP) {
     if (nk > 0) {
       gload(0, ra0, rb0);
       lstore(0, ra0, rb0);
     }
     __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
+    int64_t kt = 0;
+    auto step = [&](auto load) {
       const int buf = (int)(kt & 1);
-      if (kt + 1 < nk) gload((kt + 1) * BK, ra0, rb0);
+      load(kt + 1, ra0, rb0);
       compute(buf, 0, BK / 4);
       if (kt + 1 < nk) lstore(buf ^ 1, ra0, rb0);
       __syncthreads();
-    }
+    };
+    if (rsrc_ok)
+      for (; kt + 1 < nkf; ++kt) step(load_full);
+    for (; kt < nk; ++kt) step(load_any);
   } else {
     // k-step kt on LDS buffer kt % 2: the loads of k-step kt + 2 go into the
     // free set (rl); three quarters of the way through the MFMAs (1.8 %
@@ -306,9 +375,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     // wave finished reading before the last barrier.  The barrier waits for
     // the LDS writes only, so the loads of k-step kt + 2 stay in flight.
     auto step = [&](int64_t kt, double (&ral)[NA][2 * A_PAIRS], double (&rbl)[NB][2 * B_PAIRS],
-                    const double (&ras)[NA][2 * A_PAIRS], const double (&rbs)[NB][2 * B_PAIRS]) {
+                    const double (&ras)[NA][2 * A_PAIRS], const double (&rbs)[NB][2 * B_PAIRS], auto load) {
       const int buf = (int)(kt & 1);
-      if (kt + 2 < nk) gload((kt + 2) * BK, ral, rbl);
+      load(kt + 2, ral, rbl);
       compute(buf, 0, 3 * BK / 16);
       if (kt + 1 < nk) lstore(buf ^ 1, ras, rbs);
       compute(buf, 3 * BK / 16, BK / 4);
@@ -323,11 +392,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_s_barrier();
     int64_t kt = 0;
-    for (; kt + 1 < nk; kt += 2) {
-      step(kt, ra0, rb0, ra1, rb1);
-      step(kt + 1, ra1, rb1, ra0, rb0);
+    if (rsrc_ok) {
+      for (; kt + 3 < nkf; kt += 2) {
+        step(kt, ra0, rb0, ra1, rb1, load_full);
+        step(kt + 1, ra1, rb1, ra0, rb0, load_full);
+      }
     }
-    if (kt < nk) step(kt, ra0, rb0, ra1, rb1);
+    for (; kt + 1 < nk; kt += 2) {
+      step(kt, ra0, rb0, ra1, rb1, load_any);
+      step(kt + 1, ra1, rb1, ra0, rb0, load_any);
+    }
+    if (kt < nk) step(kt, ra0, rb0, ra1, rb1, load_any);
   }
 
   // Epilogue: P from the accumulators, then coef * P into each target.
@@ -598,6 +673,7 @@ static const TileConfig kConfigs[] = {
     {0, 0, 0, 0, 0},         // 9: retired (128 x 128 x 16, slower than 11)
     {0, 0, 0, 0, 0},         // 10: retired (as 9, two-deep)
     {128, 128, 32, 32, 32},  // 11: 16 waves, 4 waves / SIMD, one block per CU (real x real only)
+    {0, 0, 0, 0, 0},         // 12: retired (8 waves of 32 x 16, 4 waves / SIMD: slower, 2.4x the L2 misses)
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
