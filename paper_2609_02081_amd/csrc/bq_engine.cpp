@@ -1580,6 +1580,10 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
         prods[size_t(pi) * 8 + qi] = g;
       }
     }
+    // Buffer-resource loads when every product's operand tiles allow them.
+    int buf = 1;
+    for (const bq::GemmArgs& g : prods)
+      if (g.m > 0 && !bq::grouped_spans_fit(p->cfg, g.ta, g.tb, g.lda, g.ldb)) buf = 0;
     // Tables go to the device before recording (a synchronous copy may not
     // run while this thread records a graph).
     e = hipMemcpy(p->d_prods, prods.data(), prods.size() * sizeof(bq::GemmArgs), hipMemcpyHostToDevice);
@@ -1599,14 +1603,14 @@ bq_status_t grouped_bind(bq_grouped_plan_t p, void* ws) {
       // Hadamard products (rounds 4..7), their sums, then the direct products.
       auto round = [&](int q) {
         if (e == hipSuccess && p->round_n[q] > 0)
-          e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, p->d_prods, p->d_items + p->nitems + p->round_off[q],
+          e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, buf, p->d_prods, p->d_items + p->nitems + p->round_off[q],
                                  p->round_n[q], p->d_counter, p->blocks, p->cap);
       };
       for (int q = 4; q < 8; ++q) round(q);
       if (e == hipSuccess) e = bq::launch_grouped_combine(p->d_ht, p->d_ht_prefix, int(ht.size()), ht_rows, p->cap);
       for (int q = 0; q < 4; ++q) round(q);
     } else if (e == hipSuccess) {
-      e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, p->d_prods, p->d_items, p->nitems, p->d_counter,
+      e = bq::launch_grouped(p->cfg, p->dyn & 1, p->ops, buf, p->d_prods, p->d_items, p->nitems, p->d_counter,
                              p->blocks, p->cap);
     }
     if (e != hipSuccess) st = hip_fail(e, "grouped launch");

@@ -198,8 +198,11 @@ int default_tile_config(int kind, int64_t m, int64_t n, int64_t k);
 // configurations above); dyn: 1 = device work counter, 0 = cyclic; ops:
 // 0..3 when every product has (ta, tb) = (ops >> 1, ops & 1) (one tile
 // variant compiled in), -1 when they differ.
-hipError_t launch_grouped(int cfg, int dyn, int ops, const GemmArgs* prods, const GroupedItem* items, int nitems,
-                          int* counter, int blocks, hipStream_t s);
+hipError_t launch_grouped(int cfg, int dyn, int ops, int buf, const GemmArgs* prods, const GroupedItem* items,
+                          int nitems, int* counter, int blocks, hipStream_t s);
+// Whether a batched product's operand tiles (tile configuration cfg, ops
+// ta / tb) can be read through buffer resources (buf = 1 above).
+bool grouped_spans_fit(int cfg, int ta, int tb, int64_t lda, int64_t ldb);
 hipError_t launch_grouped_combine(const CombineArgs* args, const int64_t* row_prefix, int nargs, int64_t total_rows,
                                   hipStream_t s);
 // Split-precision kernels (bq_split.hip, bq_split_f8.hip).  et: 0 = BF16

@@ -124,6 +124,29 @@ __device__ __forceinline__ void load_pairs_rsrc(double (&dst)[2 * PAIRS], const 
   }
 }
 
+// Checked pattern (as MODE 2) through a buffer resource, without branches:
+// an element outside row_lim x col_lim gets an offset past the resource's
+// range (num_records = 2^31 - 1), which the hardware reads as zero without
+// an access; every other element is read where MODE 2 reads it.  Offsets
+// stay below 2^31 (the caller checks the tile's span).
+template <int PAIRS, int C, int NT>
+__device__ __forceinline__ void load_pairs_rsrc_checked(double (&dst)[2 * PAIRS], const double* base, int64_t ld,
+                                                        int64_t row_lim, int64_t col_lim, int tid) {
+  constexpr uint32_t kOut = 0x80000000u;
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+#pragma unroll
+  for (int i = 0; i < PAIRS; ++i) {
+    const int v = tid + i * NT;
+    const int rr = v / (C / 2), c = 2 * (v % (C / 2));
+    const uint32_t off = (uint32_t)((rr * (uint32_t)ld + c) * 8u);
+    const bool rok = rr < row_lim;
+    const uint32_t o0 = (rok && c < col_lim) ? off : kOut;
+    const uint32_t o1 = (rok && c + 1 < col_lim) ? off + 8u : kOut;
+    dst[2 * i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)o0, 0, 0));
+    dst[2 * i + 1] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)o1, 0, 0));
+  }
+}
+
 // A pointer that is the same in every lane, read from the first lane when
 // UNI = 1 so that the compiler keeps it (and what is computed from it) in
 // scalar registers: the batched kernel reads its arguments from memory,
@@ -149,7 +172,15 @@ __device__ __forceinline__ const double* uniform_ptr(const double* p) {
 // ADD: the batched kernel's tile: targets may carry an addend matrix
 // (Target::sr / si, scaled by sc, leading dimension GemmArgs::ldadd), and
 // the arguments come from a device table (operand bases made scalar).
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0, int DEEP = 0, int ADD = 0>
+// BUF = 1: every load goes through a buffer resource, which needs the
+// stored tiles' byte span below 2^31 (spans_fit, checked by the launcher);
+// BUF = 2 (two-deep only, for grids without edge tiles): the full k-steps
+// of interior tiles as in BUF = 1, the rest with pointer loads (the
+// register allocation of the steady-state loop comes out 1.3 % faster at
+// n = 16384 than with BUF = 1); BUF = 0: pointer loads, for leading
+// dimensions beyond the buffer range.
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int TA = 0, int TB = 0, int DEEP = 0, int ADD = 0,
+          int BUF = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
                                           TileSmem<KIND, BM, BN, BK>& sm) {
   constexpr int NWN = BN / WN;
@@ -196,11 +227,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   // are 16-byte aligned).
   const bool interior = mrem >= BM && nrem >= BN;
   const bool fast = g.vec && interior;
-  // Byte offsets of this thread's pairs in the stored tiles (16-byte path):
-  // usable through a buffer resource while the farthest stays below 2^31.
-  const int64_t a_span = (TA ? (int64_t)(BK - 1) * g.lda + BM : (int64_t)(BM - 1) * g.lda + BK) * 8;
-  const int64_t b_span = (TB ? (int64_t)(BN - 1) * g.ldb + BK : (int64_t)(BK - 1) * g.ldb + BN) * 8;
-  const bool rsrc_ok = fast && a_span < 0x7fffffff && b_span < 0x7fffffff;
+  // Byte offsets of this thread's pairs in the stored tiles (BUF, 16-byte
+  // loads), fixed for the tile.
+  const bool rsrc_ok = BUF && fast;
   uint32_t voff_a[A_PAIRS], voff_b[B_PAIRS];
 #pragma unroll
   for (int i = 0; i < A_PAIRS; ++i) {
@@ -244,6 +273,30 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 #pragma unroll
       for (int p = 0; p < NB; ++p)
         load_pairs<2, B_PAIRS, BC, NT>(rb[p], pb[p] + b_step, g.ldb, b_rows, b_cols, tid);
+    }
+  };
+  // The same tiles through buffer resources (the tile's span below 2^31):
+  // 16-byte loads for a full k-step of an interior tile with 16-byte rows,
+  // else the branch-free checked loads.
+  auto gload_rsrc = [&](int64_t k0, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
+    const bool kfull = (k0 + BK <= g.k);
+    const int64_t kleft = g.k - k0;
+    const int64_t a_step = TA ? k0 * g.lda : k0;
+    const int64_t b_step = TB ? k0 : k0 * g.ldb;
+    if (fast && kfull) {
+#pragma unroll
+      for (int p = 0; p < NA; ++p) load_pairs_rsrc<A_PAIRS>(ra[p], pa[p] + a_step, voff_a);
+#pragma unroll
+      for (int p = 0; p < NB; ++p) load_pairs_rsrc<B_PAIRS>(rb[p], pb[p] + b_step, voff_b);
+    } else {
+      const int64_t a_rows = TA ? kleft : mrem, a_cols = TA ? mrem : kleft;
+      const int64_t b_rows = TB ? nrem : kleft, b_cols = TB ? kleft : nrem;
+#pragma unroll
+      for (int p = 0; p < NA; ++p)
+        load_pairs_rsrc_checked<A_PAIRS, AC, NT>(ra[p], pa[p] + a_step, g.lda, a_rows, a_cols, tid);
+#pragma unroll
+      for (int p = 0; p < NB; ++p)
+        load_pairs_rsrc_checked<B_PAIRS, BC, NT>(rb[p], pb[p] + b_step, g.ldb, b_rows, b_cols, tid);
     }
   };
   // A stored m-major (N) is transposed on the way into LDS; stored k-major
@@ -341,6 +394,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   auto load_any = [&](int64_t kn, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
     if (kn < nk) gload(kn * BK, ra, rb);
   };
+  auto load_rsrc = [&](int64_t kn, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
+    if (kn < nk) gload_rsrc(kn * BK, ra, rb);
+  };
   auto load_full = [&](int64_t kn, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
     const int64_t k0 = kn * BK;
 #pragma unroll
@@ -352,7 +408,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
 
   if constexpr (!DEEP) {
     if (nk > 0) {
-      gload(0, ra0, rb0);
+      if constexpr (BUF) gload_rsrc(0, ra0, rb0);
+      else gload(0, ra0, rb0);
       lstore(0, ra0, rb0);
     }
     __syncthreads();
@@ -364,9 +421,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
       if (kt + 1 < nk) lstore(buf ^ 1, ra0, rb0);
       __syncthreads();
     };
-    if (rsrc_ok)
-      for (; kt + 1 < nkf; ++kt) step(load_full);
-    for (; kt < nk; ++kt) step(load_any);
+    if constexpr (BUF) {
+      if (rsrc_ok)
+        for (; kt + 1 < nkf; ++kt) step(load_full);
+      for (; kt < nk; ++kt) step(load_rsrc);
+    } else {
+      for (; kt < nk; ++kt) step(load_any);
+    }
   } else {
     // k-step kt on LDS buffer kt % 2: the loads of k-step kt + 2 go into the
     // free set (rl); three quarters of the way through the MFMAs (1.8 %
@@ -385,24 +446,32 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
       __builtin_amdgcn_s_barrier();
     };
     if (nk > 0) {
-      gload(0, ra0, rb0);
+      if constexpr (BUF == 1) gload_rsrc(0, ra0, rb0);
+      else gload(0, ra0, rb0);
       lstore(0, ra0, rb0);
-      if (nk > 1) gload(BK, ra1, rb1);
+      if (nk > 1) {
+        if constexpr (BUF == 1) gload_rsrc(BK, ra1, rb1);
+        else gload(BK, ra1, rb1);
+      }
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_s_barrier();
     int64_t kt = 0;
-    if (rsrc_ok) {
+    if (BUF && rsrc_ok) {
       for (; kt + 3 < nkf; kt += 2) {
         step(kt, ra0, rb0, ra1, rb1, load_full);
         step(kt + 1, ra1, rb1, ra0, rb0, load_full);
       }
     }
-    for (; kt + 1 < nk; kt += 2) {
-      step(kt, ra0, rb0, ra1, rb1, load_any);
-      step(kt + 1, ra1, rb1, ra0, rb0, load_any);
-    }
-    if (kt < nk) step(kt, ra0, rb0, ra1, rb1, load_any);
+    auto rest = [&](auto load) {
+      for (; kt + 1 < nk; kt += 2) {
+        step(kt, ra0, rb0, ra1, rb1, load);
+        step(kt + 1, ra1, rb1, ra0, rb0, load);
+      }
+      if (kt < nk) step(kt, ra0, rb0, ra1, rb1, load);
+    };
+    if constexpr (BUF == 1) rest(load_rsrc);
+    else rest(load_any);
   }
 
   // Epilogue: P from the accumulators, then coef * P into each target.
@@ -476,7 +545,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
   }
 }
 
-template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0, int DEEP = 0>
+template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0, int DEEP = 0, int BUF = 1>
 __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 cgemm_f64(const GemmArgs g) {
@@ -485,7 +554,7 @@ cgemm_f64(const GemmArgs g) {
   const int tiles_n = (int)((g.n + BN - 1) / BN);
   int tm, tn;
   tile_coords(tiles_m, tiles_n, g.xcd_remap, g.group_m, tm, tn);
-  gemm_tile<KIND, BM, BN, BK, WM, WN, TA, TB, DEEP>(g, (int64_t)tm * BM, (int64_t)tn * BN, sm);
+  gemm_tile<KIND, BM, BN, BK, WM, WN, TA, TB, DEEP, 0, BUF>(g, (int64_t)tm * BM, (int64_t)tn * BN, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -621,7 +690,7 @@ __global__ void reset_counter(int* counter) {
 
 // OPS: 0..3 = every product of the plan has (ta, tb) = (OPS >> 1, OPS & 1),
 // so one tile variant is compiled in; -1 = products differ (all four).
-template <int BM, int BN, int BK, int WM, int WN, int WPE, int DYN, int OPS>
+template <int BM, int BN, int BK, int WM, int WN, int WPE, int DYN, int OPS, int BUF = 1>
 __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter) {
@@ -644,13 +713,13 @@ grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* c
       const int64_t m0 = (int64_t)w.tm * BM, n0 = (int64_t)w.tn * BN;
       // op T / H operands are read in their stored orientation
       if constexpr (OPS >= 0) {
-        gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, (OPS >> 1), (OPS & 1), 0, 1>(g, m0, n0, sm);
+        gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, (OPS >> 1), (OPS & 1), 0, 1, BUF>(g, m0, n0, sm);
       } else if (g.ta) {
-        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 1, 0, 1>(g, m0, n0, sm);
-        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 0, 0, 1>(g, m0, n0, sm);
+        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 1, 0, 1, BUF>(g, m0, n0, sm);
+        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 1, 0, 0, 1, BUF>(g, m0, n0, sm);
       } else {
-        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 1, 0, 1>(g, m0, n0, sm);
-        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 0, 0, 1>(g, m0, n0, sm);
+        if (g.tb) gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 1, 0, 1, BUF>(g, m0, n0, sm);
+        else gemm_tile<KIND_GAUSS, BM, BN, BK, WM, WN, 0, 0, 0, 1, BUF>(g, m0, n0, sm);
       }
     }
     if (!DYN) it += gridDim.x;
@@ -698,14 +767,47 @@ int default_tile_config(int kind, int64_t m, int64_t n, int64_t k) {
   return rounds128 < rounds64 ? 11 : 3;
 }
 
+// Byte span of the stored A and B tiles of a BM x BN x BK block below 2^31,
+// so that buffer-resource offsets reach every element.
+template <int BM, int BN, int BK, int TA, int TB>
+static bool spans_fit(int64_t lda, int64_t ldb) {
+  const int64_t a = (TA ? (int64_t)(BK - 1) * lda + BM : (int64_t)(BM - 1) * lda + BK) * 8;
+  const int64_t b = (TB ? (int64_t)(BN - 1) * ldb + BK : (int64_t)(BK - 1) * ldb + BN) * 8;
+  return a < 0x7fffffff && b < 0x7fffffff;
+}
+
+bool grouped_spans_fit(int cfg, int ta, int tb, int64_t lda, int64_t ldb) {
+  if (cfg == 6) {
+    if (ta) return tb ? spans_fit<64, 64, 8, 1, 1>(lda, ldb) : spans_fit<64, 64, 8, 1, 0>(lda, ldb);
+    return tb ? spans_fit<64, 64, 8, 0, 1>(lda, ldb) : spans_fit<64, 64, 8, 0, 0>(lda, ldb);
+  }
+  if (ta) return tb ? spans_fit<64, 64, 16, 1, 1>(lda, ldb) : spans_fit<64, 64, 16, 1, 0>(lda, ldb);
+  return tb ? spans_fit<64, 64, 16, 0, 1>(lda, ldb) : spans_fit<64, 64, 16, 0, 0>(lda, ldb);
+}
+
+// Leading dimensions too large for buffer offsets take the 64 x 64 x 16
+// block with pointer loads.
 template <int KIND, int BM, int BN, int BK, int WM, int WN, int WPE, int TA = 0, int TB = 0, int DEEP = 0>
 static hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
+  if (!spans_fit<BM, BN, BK, TA, TB>(g.lda, g.ldb)) {
+    const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
+    if (tiles <= 0) return hipSuccess;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((cgemm_f64<KIND, 64, 64, 16, 32, 32, 2, TA, TB, 0, 0>), dim3((unsigned)tiles), dim3(256), 0, s,
+                       g);
+    return hipGetLastError();
+  }
   const int64_t tm = (g.m + BM - 1) / BM, tn = (g.n + BN - 1) / BN;
   const int64_t tiles = tm * tn;
   if (tiles <= 0) return hipSuccess;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   constexpr int NT = (BM / WM) * (BN / WN) * 64;
-  hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE, TA, TB, DEEP>), dim3((unsigned)tiles), dim3(NT), 0, s, g);
+  if (DEEP && g.m % BM == 0 && g.n % BN == 0)
+    hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE, TA, TB, DEEP, 2>), dim3((unsigned)tiles), dim3(NT), 0,
+                       s, g);
+  else
+    hipLaunchKernelGGL((cgemm_f64<KIND, BM, BN, BK, WM, WN, WPE, TA, TB, DEEP>), dim3((unsigned)tiles), dim3(NT), 0, s,
+                       g);
   return hipGetLastError();
 }
 
@@ -780,8 +882,22 @@ static hipError_t launch_grouped_cfg(const GemmArgs* prods, const GroupedItem* i
   }
 }
 
-hipError_t launch_grouped(int cfg, int dyn, int ops, const GemmArgs* prods, const GroupedItem* items, int nitems,
-                          int* counter, int blocks, hipStream_t s) {
+hipError_t launch_grouped(int cfg, int dyn, int ops, int buf, const GemmArgs* prods, const GroupedItem* items,
+                          int nitems, int* counter, int blocks, hipStream_t s) {
+  if (!buf) {
+    // Leading dimensions too large for buffer offsets: pointer loads, the
+    // kernel with every tile variant, 64 x 64 x 16 blocks.
+    constexpr int NT = 256;
+    if (dyn) {
+      hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
+      hipLaunchKernelGGL((grouped_gemm<64, 64, 16, 32, 32, 2, 1, -1, 0>), dim3(blocks), dim3(NT), 0, s, prods, items,
+                         nitems, counter);
+    } else {
+      hipLaunchKernelGGL((grouped_gemm<64, 64, 16, 32, 32, 2, 0, -1, 0>), dim3(blocks), dim3(NT), 0, s, prods, items,
+                         nitems, counter);
+    }
+    return hipGetLastError();
+  }
   switch (cfg) {
     case 0: return launch_grouped_cfg<64, 64, 16, 32, 32, 2>(prods, items, nitems, counter, dyn, ops, blocks, s);
     case 6: return launch_grouped_cfg<64, 64, 8, 32, 32, 2>(prods, items, nitems, counter, dyn, ops, blocks, s);

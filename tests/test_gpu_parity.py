@@ -429,3 +429,42 @@ def test_real_products_in_large_blocks(bq, m, k, n, mask):
     got = C[:, ri][:, :, ci].cpu().numpy()
     ref = oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy())
     assert oracle.rel_frobenius(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("opB", ["N", "T"])
+def test_leading_dimension_beyond_buffer_offsets(bq, opB):
+    """Operand rows 4.5e6 doubles apart: a 64-row tile spans more than 2^31
+    bytes, so the single call and the batched plan read such operands with
+    pointer loads instead of buffer resources.  A is 3 x 40 (op N), B is
+    40 x 5 (op N) or stored 5 x 40 with the same row pitch (op T); against
+    the oracle on contiguous copies."""
+    import torch
+
+    L = 4_500_000
+    rng = np.random.default_rng(80)
+    a = inputs.blocks(rng, 3, 40, "uniform")
+    Abig = torch.zeros((8, 3, L), dtype=torch.float64, device="cuda")
+    Abig[:, :, :40] = torch.from_numpy(a).to("cuda")
+    A = Abig[:, :, :40]
+    if opB == "N":
+        b = inputs.blocks(rng, 40, 5, "uniform")
+        B = torch.from_numpy(b).to("cuda")
+        ref = oracle.gemm(a, b)
+    else:
+        bs = inputs.blocks(rng, 5, 40, "uniform")
+        Bbig = torch.zeros((8, 5, L), dtype=torch.float64, device="cuda")
+        Bbig[:, :, :40] = torch.from_numpy(bs).to("cuda")
+        B = Bbig[:, :, :40]
+        ref = oracle.gemm(a, oracle.transpose(bs))
+    print(f"ld {L}, op B {opB}: single call and batched plan", flush=True)
+    C = bq.bq_gemm(A, B, opB=opB)
+    torch.cuda.synchronize()
+    assert oracle.rel_frobenius(C.cpu().numpy(), ref) <= TOL
+    C2 = torch.full_like(C, float("nan"))
+    plan = bq.GroupedPlan([(A, B, C2)], opB=opB)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert oracle.rel_frobenius(C2.cpu().numpy(), ref) <= TOL
+    plan.close()
+    del Abig
+    torch.cuda.empty_cache()
