@@ -103,7 +103,7 @@ def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, copy_bytes
         raise SystemExit(f"missing counters: {f_kib} {w_kib} {cf} {cw}")
     kf = copy_bytes / (cf * 1024.0)
     kw = copy_bytes / (cw * 1024.0)
-    out = {"kernel": "cgemm_f64<GAUSS> (tile config 0)", "workload": "n=16384 biquaternion product",
+    out = {"kernel": "cgemm_f64<GAUSS> (default tile configuration)", "workload": "n=16384 biquaternion product",
            "kernel_source_sha256": kernel_sha(),
            "dispatches": [nf, nw],
            "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
@@ -755,6 +755,7 @@ def main():
                     help="only time the oracle in full on the host (n = 256, 1 and all threads; n = 4096 x 4 masks)")
     ap.add_argument("--power-probe", default="",
                     help="only record power and clock while these forms run back to back (e.g. fp64,split_int8_crt)")
+    ap.add_argument("--probe-seconds", type=float, default=12.0, help="duration of each --power-probe form")
     ap.add_argument("--summarize-config4", nargs=3, metavar=("JSON", "OUT_MD", "COMMAND"),
                     help="markdown table of a --config4 run's JSON output")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -801,7 +802,8 @@ def main():
         return
     if args.power_probe:
         precs = [x for x in args.power_probe.split(",") if x]
-        print(json.dumps({"power_probe": power_probe(bq, inputs, torch, n, precs, 12.0, log)}), flush=True)
+        print(json.dumps({"power_probe": power_probe(bq, inputs, torch, n, precs, args.probe_seconds, log)}),
+              flush=True)
         return
     log(f"building Hermitian inputs n={n} on the device")
     t0 = time.time()
