@@ -468,3 +468,25 @@ def test_leading_dimension_beyond_buffer_offsets(bq, opB):
     plan.close()
     del Abig
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("m,k,n", [(2050, 1030, 2060), (2047, 1041, 2049)])
+def test_two_deep_with_edge_tiles(bq, m, k, n):
+    """Complex products large enough for the two-deep pipeline (k >= 1024,
+    at least 1024 tiles) on grids with edge tiles: interior tiles take the
+    buffer-load steady state, edge tiles and the ragged last k-step the
+    bounds-checked buffer loads; sampled rows and columns (the last ones
+    included) against the oracle."""
+    import torch
+
+    rng = np.random.default_rng(m + n)
+    A = torch.from_numpy(inputs.blocks(rng, m, k, "uniform")).to("cuda")
+    B = torch.from_numpy(inputs.blocks(rng, k, n, "uniform")).to("cuda")
+    print(f"two-deep with edge tiles {m}x{k}x{n}", flush=True)
+    C = bq.bq_gemm(A, B)
+    torch.cuda.synchronize()
+    rows, cols = _sample(m, 40, 73), _sample(n, 40, 74)
+    ri, ci = torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")
+    got = C[:, ri][:, :, ci].cpu().numpy()
+    ref = oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy())
+    assert oracle.rel_frobenius(got, ref) <= TOL
