@@ -147,6 +147,35 @@ __device__ __forceinline__ void load_pairs_rsrc_checked(double (&dst)[2 * PAIRS]
   }
 }
 
+// Full k-step of any tile (edge tiles, rows that are not 16-byte aligned)
+// through a buffer resource whose range ends at the operand's last element:
+// pairs past the range read as zero without an access.  VEC: 16-byte loads
+// (base and rows 16-byte aligned; the range is rounded up to 16 bytes, so a
+// load lies wholly inside or wholly past it); else two 8-byte loads per
+// pair.  The offsets are those of load_pairs_rsrc.  Rows or columns of an
+// edge tile that lie outside the matrix fall past the range, or on the
+// matrix's own elements (or the 8 bytes that share the last element's
+// 16-byte chunk), which feed only outputs outside the matrix, never stored;
+// the k range of a full k-step lies inside the matrix.
+template <int PAIRS, int VEC>
+__device__ __forceinline__ void load_pairs_rsrc_range(double (&dst)[2 * PAIRS], const double* base, int64_t extent,
+                                                      const uint32_t (&voff)[PAIRS]) {
+  const int64_t rounded = VEC ? ((extent + 15) & ~(int64_t)15) : extent;
+  const int range = (int)(rounded < 0x7fffffff ? rounded : 0x7fffffff);
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, range, 0x00020000);
+#pragma unroll
+  for (int i = 0; i < PAIRS; ++i) {
+    if constexpr (VEC) {
+      const d2 x = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff[i], 0, 0));
+      dst[2 * i] = x[0];
+      dst[2 * i + 1] = x[1];
+    } else {
+      dst[2 * i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff[i], 0, 0));
+      dst[2 * i + 1] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(voff[i] + 8u), 0, 0));
+    }
+  }
+}
+
 // A pointer that is the same in every lane, read from the first lane when
 // UNI = 1 so that the compiler keeps it (and what is computed from it) in
 // scalar registers: the batched kernel reads its arguments from memory,
@@ -426,8 +455,39 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
       __syncthreads();
     };
     if constexpr (BUF) {
-      if (rsrc_ok)
+      if constexpr (ADD) {
+        // Batched tiles: the full k-steps of every tile (a batch holds
+        // many edge tiles and odd leading dimensions) run the unchecked
+        // loop, within the operands' extents.
+        if (a_span < 0x7fffffff && b_span < 0x7fffffff) {
+          // Byte extent of each stored operand from the tile's base to its
+          // last element.
+          const int64_t a_ext = (TA ? (g.k - 1) * g.lda + mrem : (mrem - 1) * g.lda + g.k) * 8;
+          const int64_t b_ext = (TB ? (nrem - 1) * g.ldb + g.k : (g.k - 1) * g.ldb + nrem) * 8;
+          auto load_range = [&](int64_t kn, double (&ra)[NA][2 * A_PAIRS], double (&rb)[NB][2 * B_PAIRS]) {
+            const int64_t a_step = TA ? kn * BK * g.lda : kn * BK;
+            const int64_t b_step = TB ? kn * BK : kn * BK * g.ldb;
+            if (g.vec) {
+#pragma unroll
+              for (int p = 0; p < NA; ++p)
+                load_pairs_rsrc_range<A_PAIRS, 1>(ra[p], pa[p] + a_step, a_ext - a_step * 8, voff_a);
+#pragma unroll
+              for (int p = 0; p < NB; ++p)
+                load_pairs_rsrc_range<B_PAIRS, 1>(rb[p], pb[p] + b_step, b_ext - b_step * 8, voff_b);
+            } else {
+#pragma unroll
+              for (int p = 0; p < NA; ++p)
+                load_pairs_rsrc_range<A_PAIRS, 0>(ra[p], pa[p] + a_step, a_ext - a_step * 8, voff_a);
+#pragma unroll
+              for (int p = 0; p < NB; ++p)
+                load_pairs_rsrc_range<B_PAIRS, 0>(rb[p], pb[p] + b_step, b_ext - b_step * 8, voff_b);
+            }
+          };
+          for (; kt + 1 < nkf; ++kt) step(load_range);
+        }
+      } else if (rsrc_ok) {
         for (; kt + 1 < nkf; ++kt) step(load_full);
+      }
       for (; kt < nk; ++kt) step(load_rsrc);
     } else {
       for (; kt < nk; ++kt) step(load_any);
@@ -697,7 +757,7 @@ __global__ void reset_counter(int* counter) {
 template <int BM, int BN, int BK, int WM, int WN, int WPE, int DYN, int OPS, int BUF = 1>
 __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* counter) {
+grouped_gemm(const GemmArgs* __restrict__ prods, const GroupedItem* __restrict__ items, int nitems, int* counter) {
   __shared__ TileSmem<KIND_GAUSS, BM, BN, BK> sm;
   __shared__ int next;
   int it = blockIdx.x;
@@ -705,7 +765,10 @@ grouped_gemm(const GemmArgs* prods, const GroupedItem* items, int nitems, int* c
     if (DYN) {
       if (threadIdx.x == 0) next = atomicAdd(counter, 1);
       __syncthreads();
-      it = next;
+      // from the first lane: the item (and the product's arguments read
+      // through it) is then known to be uniform and loaded into scalar
+      // registers once per tile
+      it = __builtin_amdgcn_readfirstlane(next);
       __syncthreads();
     }
     if (it >= nitems) break;

@@ -264,3 +264,47 @@ def test_uniform_op_batches(bq, oa, ob):
         torch.cuda.synchronize()
         assert oracle.rel_frobenius(C.cpu().numpy(), single.cpu().numpy()) <= 1e-15, (oa, ob, shape)
     plan.close()
+
+
+def _padded(data, pad, torch):
+    """(8, rows, cols) device view of `data` inside a buffer with `pad` NaN
+    columns after each row (leading dimension cols + pad)."""
+    rows, cols = data.shape[1], data.shape[2]
+    buf = torch.full((8, rows, cols + pad), float("nan"), dtype=torch.float64, device="cuda")
+    buf[:, :, :cols] = torch.from_numpy(data).to("cuda")
+    return buf[:, :, :cols]
+
+
+@pytest.mark.parametrize("oa,ob", [("N", "N"), ("T", "H"), ("H", "N"), ("C", "T")])
+def test_padded_operands_with_nan_padding(bq, oa, ob):
+    """Operands whose rows are padded (odd and even leading dimensions, odd
+    and even stored widths) with NaN in the padding, edge tiles on both
+    sides and several full k-steps: the batched tiles read their full
+    k-steps without bounds checks, and padding may reach only outputs
+    outside the matrix, never stored.  Every product is finite and matches
+    the oracle on the unpadded operands and the single call."""
+    import torch
+
+    rng = np.random.default_rng(66)
+    shapes = [(77, 80, 45), (130, 97, 66), (64, 48, 129), (33, 160, 31), (100, 64, 100), (65, 130, 70)]
+    pads = [1, 2, 3, 6, 0, 5]
+    probs, refs = [], []
+    for (m, k, n), pad in zip(shapes, pads):
+        a = inputs.blocks(rng, *((k, m) if oa in "TH" else (m, k)))
+        b = inputs.blocks(rng, *((n, k) if ob in "TH" else (k, n)))
+        A, B = _padded(a, pad, torch), _padded(b, pad + 1, torch)
+        C = torch.full((8, m, n), float("nan"), dtype=torch.float64, device="cuda")
+        probs.append((A, B, C))
+        refs.append(oracle.gemm(OP_FN[oa](a), OP_FN[ob](b)))
+    print(f"padded operands, op {oa}{ob}", flush=True)
+    plan = bq.GroupedPlan(probs, opA=oa, opB=ob)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (A, B, C), ref, shape in zip(probs, refs, shapes):
+        c = C.cpu().numpy()
+        assert np.all(np.isfinite(c)), shape
+        assert oracle.rel_frobenius(c, ref) <= TOL, shape
+        single = bq.bq_gemm(A, B, opA=oa, opB=ob)
+        torch.cuda.synchronize()
+        assert oracle.rel_frobenius(c, single.cpu().numpy()) <= 1e-15, shape
+    plan.close()
