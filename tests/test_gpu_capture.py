@@ -5,10 +5,10 @@
   the graph is replayed several times with eager work and synchronizations
   in between, and every replay is checked against the eager result.
 * Misuse: a batched plan's first launch copies its tables synchronously
-  (through the legacy stream) before recording on its own stream; while the
-  thread captures another stream in global mode the runtime refuses that
-  (the legacy stream would depend on a capturing stream), and the plan
-  reports BQ_ERR_HIP (code 5).
+  (through the legacy stream) before recording on its own stream; while
+  another stream captures in global mode the runtime refuses that (the
+  legacy stream would depend on a capturing stream), and the plan reports
+  BQ_ERR_HIP (code 5).
 """
 import numpy as np
 import pytest
@@ -76,11 +76,17 @@ def test_captured_product_replays(bq, entry):
 def test_plan_recording_during_global_capture_is_reported(bq):
     """A batched plan records its graph on its own stream at its first
     launch, after copying its tables to the device through the legacy
-    stream; while the thread captures another stream in global mode the
-    runtime refuses that copy, and the plan reports BQ_ERR_HIP (code 5).
-    After the capture is discarded the same plan launches and is correct."""
+    stream; while another stream captures in global mode the runtime
+    refuses that copy, and the plan reports BQ_ERR_HIP (code 5).  After the
+    capture is ended the same plan launches and is correct.  The capture is
+    begun and ended through the HIP runtime itself, so that torch's caching
+    allocator never routes allocations to a capture pool that an invalidated
+    capture would leave in place."""
+    import ctypes
+
     import torch
 
+    hip = ctypes.CDLL("libamdhip64.so")
     m, k, n = 64, 64, 64
     A, B = _operands(m, k, n, 91)
     C = torch.full((8, m, n), float("nan"), dtype=torch.float64, device="cuda")
@@ -88,22 +94,21 @@ def test_plan_recording_during_global_capture_is_reported(bq):
     ws = plan.workspace()
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
-    g = torch.cuda.CUDAGraph()
+    h = ctypes.c_void_p(s.cuda_stream)
     print("batched plan recorded during a global capture", flush=True)
     code = None
-    with torch.cuda.stream(s):
-        g.capture_begin(capture_error_mode="global")
-        try:
-            plan.launch(workspace=ws)
-        except bq.BqError as e:
-            code = e.code
-            print(f"reported: {e}", flush=True)
-        finally:
-            try:
-                g.capture_end()
-            except RuntimeError:
-                pass  # the runtime invalidated the capture
-    del g
+    assert hip.hipStreamBeginCapture(h, 0) == 0  # hipStreamCaptureModeGlobal
+    try:
+        plan.launch(workspace=ws, stream=s)
+    except bq.BqError as e:
+        code = e.code
+        print(f"reported: {e}", flush=True)
+    finally:
+        graph = ctypes.c_void_p()
+        rc = hip.hipStreamEndCapture(h, ctypes.byref(graph))
+        if rc == 0 and graph.value:
+            hip.hipGraphDestroy(graph)
+        hip.hipGetLastError()  # the invalidated capture's error is not left for later calls
     torch.cuda.synchronize()
     assert code == 5
     plan.launch(workspace=ws)

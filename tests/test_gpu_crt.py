@@ -250,6 +250,7 @@ def test_n24576_hermitian_sampled(bq):
     n = 24576
     print(f"crt n={n}: building Hermitian inputs on the device", flush=True)
     A, B = inputs.hermitian_pair(n, 3, "cuda")
+    torch.cuda.empty_cache()  # the builder's temporaries, before the workspace
     C = bq.bq_gemm(A, B, prec=PREC)
     torch.cuda.synchronize()
     print(f"crt n={n}: product done", flush=True)

@@ -356,6 +356,7 @@ def test_large_hermitian(bq, n, streamed):
 
     print(f"n={n} streamed={streamed}: building Hermitian inputs on the device", flush=True)
     A, B = inputs.hermitian_pair(n, 3, "cuda")
+    torch.cuda.empty_cache()  # the builder's temporaries, before the workspace
     C = bq.bq_gemm(A, B, streamed=streamed)
     torch.cuda.synchronize()
     print(f"n={n}: product done", flush=True)
