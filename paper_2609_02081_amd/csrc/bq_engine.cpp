@@ -540,9 +540,9 @@ bq_status_t validate(bq_op_t opA, bq_op_t opB, const bq_matrix_t* A, const bq_ma
 }
 
 // Tile order of the single-call GEMM: each XCD takes a contiguous range of
-// tiles, walked in groups of 4 tile rows (groups of 2, 4 and 8 tie at
-// n = 16384; at n = 22000 4 is 2 % faster than 8).  BQ_TILE_ORDER="xcd,group"
-// overrides.
+// tiles, walked in groups of 4 tile rows (at n = 16384 and 24576 groups of
+// 2 and 8 are 0.7-2 % slower, of 16 5-6 %, and without the XCD ranges the
+// product is 8-10 % slower).  BQ_TILE_ORDER="xcd,group" overrides.
 void tile_order(int* xcd, int* group) {
   *xcd = 1;
   *group = 4;
