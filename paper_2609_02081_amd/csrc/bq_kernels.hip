@@ -456,6 +456,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
     };
     if constexpr (BUF) {
       if constexpr (ADD) {
+        // A wave whose part of an edge tile lies wholly outside the matrix
+        // skips its MFMAs (its results are never stored), so the other
+        // block's wave on its SIMD has the matrix pipe to itself.
+        const bool wave_live =
+            __builtin_amdgcn_readfirstlane(wm0) < mrem && __builtin_amdgcn_readfirstlane(wn0) < nrem;
+        auto step_live = [&](auto load) {
+          const int buf = (int)(kt & 1);
+          load(kt + 1, ra0, rb0);
+          if (wave_live) compute(buf, 0, BK / 4);
+          if (kt + 1 < nk) lstore(buf ^ 1, ra0, rb0);
+          __syncthreads();
+        };
         // Batched tiles: the full k-steps of every tile (a batch holds
         // many edge tiles and odd leading dimensions) run the unchecked
         // loop, within the operands' extents.
@@ -483,12 +495,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                 load_pairs_rsrc_range<B_PAIRS, 0>(rb[p], pb[p] + b_step, b_ext - b_step * 8, voff_b);
             }
           };
-          for (; kt + 1 < nkf; ++kt) step(load_range);
+          for (; kt + 1 < nkf; ++kt) step_live(load_range);
         }
-      } else if (rsrc_ok) {
-        for (; kt + 1 < nkf; ++kt) step(load_full);
+        for (; kt < nk; ++kt) step_live(load_rsrc);
+      } else {
+        if (rsrc_ok)
+          for (; kt + 1 < nkf; ++kt) step(load_full);
+        for (; kt < nk; ++kt) step(load_rsrc);
       }
-      for (; kt < nk; ++kt) step(load_rsrc);
     } else {
       for (; kt < nk; ++kt) step(load_any);
     }
