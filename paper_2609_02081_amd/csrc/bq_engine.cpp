@@ -985,7 +985,7 @@ bq_status_t execute(bq_handle_t h, const Plan& pl, const Prec& pr, const bq_matr
       g.tgt[g.ntgt++] = T;
     }
     if (g.ntgt == 0) continue;
-    const int cfg = cfg_override >= 0 ? cfg_override : bq::default_tile_config(kind, m, n, k);
+    const int cfg = bq::tile_config_for(kind, cfg_override, m, n, k);
     const int nprod = kind == bq::KIND_GAUSS ? 3 : (kind == bq::KIND_RR ? 1 : 2);
     Tracer tr(h, s, kind, cfg, m, n, k, double(nprod) * 2.0 * double(m) * double(n) * double(k), 0.0);
     hipError_t e = bq::launch_cgemm(kind, g, cfg, s);

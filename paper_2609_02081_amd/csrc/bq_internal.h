@@ -194,6 +194,10 @@ hipError_t launch_fill_zero(double* p, int64_t rows, int64_t cols, int64_t ld, h
 int num_tile_configs();
 TileConfig tile_config(int cfg);
 int default_tile_config(int kind, int64_t m, int64_t n, int64_t k);
+// The configuration a single product runs: the request where it suits the
+// kind (3 or 11 for real products; complex kinds always take 0), else the
+// default.
+int tile_config_for(int kind, int requested, int64_t m, int64_t n, int64_t k);
 // Batched form (complex x complex products only).  cfg: 0 or 6 (tile
 // configurations above); dyn: 1 = device work counter, 0 = cyclic; ops:
 // 0..3 when every product has (ta, tb) = (ops >> 1, ops & 1) (one tile

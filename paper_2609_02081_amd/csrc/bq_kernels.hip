@@ -894,38 +894,39 @@ static hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Complex kinds take configuration 0 (64 x 64 x 16), real products 3
+// (64 x 64 x 32) or 11 (128 x 128 x 32); tile_config_for maps a request to
+// one of these, and the launcher refuses any other.
 template <int KIND>
 static hipError_t launch_kind(const GemmArgs& g, int cfg, hipStream_t s) {
-  // Transposed operands (op T or H) run the default tile configuration.
+  // Transposed operands (op T or H) run the 64 x 64 x 16 tile.
   if (g.ta || g.tb) {
     if (g.ta && g.tb) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 1, 1>(g, s);
     if (g.ta) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 1, 0>(g, s);
     return launch_one<KIND, 64, 64, 16, 32, 32, 2, 0, 1>(g, s);
   }
-  switch (cfg) {
-    case 0:
-      // Large complex products take the two-deep pipeline (1 % faster at
-      // n = 16384); short k loops and small grids do better without it.
-      if constexpr (KIND == KIND_GAUSS) {
-        const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
-        if (g.k >= 1024 && tiles >= 1024) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 0, 0, 1>(g, s);
-      }
-      return launch_one<KIND, 64, 64, 16, 32, 32, 2>(g, s);
-    case 3:
-      // Real products (one accumulator set) the same way.
-      if constexpr (KIND == KIND_RR) {
-        const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
-        if (g.k >= 1024 && tiles >= 1024) return launch_one<KIND, 64, 64, 32, 32, 32, 2, 0, 0, 1>(g, s);
-      }
-      return launch_one<KIND, 64, 64, 32, 32, 32, 2>(g, s);
-    case 6: return launch_one<KIND, 64, 64, 8, 32, 32, 2>(g, s);
-    case 11:
-      // 128 x 128 blocks for real products only (one A and one B tile in
-      // LDS: 135 KB); the complex kinds take configuration 0.
-      if constexpr (KIND == KIND_RR) return launch_one<KIND, 128, 128, 32, 32, 32, 4>(g, s);
-      return launch_kind<KIND>(g, 0, s);
-    default: return hipErrorInvalidValue;
+  const int64_t tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
+  if constexpr (KIND == KIND_RR) {
+    // 128 x 128 blocks: one A and one B tile in LDS (135 KB), one block per CU.
+    if (cfg == 11) return launch_one<KIND, 128, 128, 32, 32, 32, 4>(g, s);
+    if (cfg != 3) return hipErrorInvalidValue;
+    // Large products take the two-deep pipeline, as the complex ones do.
+    if (g.k >= 1024 && tiles >= 1024) return launch_one<KIND, 64, 64, 32, 32, 32, 2, 0, 0, 1>(g, s);
+    return launch_one<KIND, 64, 64, 32, 32, 32, 2>(g, s);
+  } else {
+    if (cfg != 0) return hipErrorInvalidValue;
+    // Large complex products take the two-deep pipeline (1 % faster at
+    // n = 16384); short k loops and small grids do better without it.
+    if constexpr (KIND == KIND_GAUSS) {
+      if (g.k >= 1024 && tiles >= 1024) return launch_one<KIND, 64, 64, 16, 32, 32, 2, 0, 0, 1>(g, s);
+    }
+    return launch_one<KIND, 64, 64, 16, 32, 32, 2>(g, s);
   }
+}
+
+int tile_config_for(int kind, int requested, int64_t m, int64_t n, int64_t k) {
+  if (kind != KIND_RR) return 0;
+  return (requested == 3 || requested == 11) ? requested : default_tile_config(kind, m, n, k);
 }
 
 hipError_t launch_cgemm(int kind, const GemmArgs& g, int cfg, hipStream_t s) {

@@ -491,3 +491,22 @@ def test_two_deep_with_edge_tiles(bq, m, k, n):
     got = C[:, ri][:, :, ci].cpu().numpy()
     ref = oracle.gemm(A[:, ri, :].cpu().numpy(), B[:, :, ci].cpu().numpy())
     assert oracle.rel_frobenius(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("env,value", [("BQ_TILE_ORDER", "0,4"), ("BQ_TILE_ORDER", "1,1"),
+                                       ("BQ_TILE_ORDER", "1,16"), ("BQ_TILE_CONFIG", "3"),
+                                       ("BQ_TILE_CONFIG", "11"), ("BQ_TILE_CONFIG", "6")])
+def test_tuning_switches_same_products(bq, monkeypatch, env, value):
+    """The tile order and tile configuration switches change only which
+    kernel shape runs and how blocks map to tiles: a biquaternion product
+    and a real product (one component each) of integer inputs equal the
+    oracle's exactly under every setting (configuration 3 or 11 selects the
+    real products' tile, a complex product ignores it, and 6 is not a
+    single-call configuration: it is ignored)."""
+    A, B = inputs.pair(330, 200, 270, "int", seed=12, bound=1024)
+    R = inputs.MASKS["real"]
+    Ar, Br = A * (np.arange(8) == 0)[:, None, None], B * (np.arange(8) == 0)[:, None, None]
+    monkeypatch.setenv(env, value)
+    print(f"{env}={value}", flush=True)
+    assert np.array_equal(run(bq, A, B), oracle.gemm(A, B))
+    assert np.array_equal(run(bq, Ar, Br, mask_a=R, mask_b=R), oracle.gemm(Ar, Br))
